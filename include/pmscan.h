@@ -1,0 +1,132 @@
+/*
+ * pmscan.h -- C ABI of libpmscan.so, the MI355X (gfx950) k-mismatch
+ * character-class DNA scan of arXiv 1611.06115 ("Fast low-level pattern
+ * matching algorithm").
+ *
+ * The problem (paper Sect. 1.1): a text t over {A,C,G,T} and a pattern p whose
+ * positions are IUPAC character classes; report every window i whose number
+ * of positions j with t[i+j] outside p[j] is at most k (eq. (4), Sect. 2.4),
+ * with that number.  Positions are 0-based here (the paper's location i is
+ * position i-1).
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns pm_status (PM_OK = 0) or a size; no exception or
+ *    abort crosses the ABI.  pm_last_error_detail() describes the last failure
+ *    of the calling thread.
+ *  - "_dev" pointers are device (HBM) pointers owned by the caller (for
+ *    example PyTorch tensors); the library allocates no device memory in the
+ *    scan entry points and keeps no pointer after a call returns.  Host
+ *    pointers are read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  GPU
+ *    work is enqueued asynchronously on it; device-side results are valid
+ *    once the stream has been synchronised.
+ *  - Conditions detectable on the host (bad pattern symbol, m = 0, k too
+ *    large, buffers too small, null pointers) are reported synchronously.
+ *    Conditions found on the device are reported through device words the
+ *    caller reads after synchronising: the index of the first bad text
+ *    symbol, and hit totals that may exceed the output capacity.
+ */
+#ifndef PMSCAN_H
+#define PMSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pm_status;
+#define PM_OK 0
+#define PM_ERR_ARG (-1)         /* invalid argument (null pointer, m = 0, k > 65535, ...) */
+#define PM_ERR_SYMBOL (-2)      /* pattern symbol outside Table 2 / malformed class        */
+#define PM_ERR_HIP (-3)         /* a HIP runtime call failed                                */
+#define PM_ERR_WORKSPACE (-4)   /* workspace or output buffer smaller than required         */
+#define PM_ERR_UNSUPPORTED (-5) /* valid request this build cannot serve                    */
+#define PM_ERR_BUSY (-6)        /* serving engine: no free slot or memory for the query     */
+#define PM_ERR_NOT_FOUND (-7)   /* serving engine: unknown query id                          */
+
+/* Human-readable name of a status code (static storage). */
+const char* pm_status_string(pm_status s);
+/* Detail of the last failure on the calling thread (thread-local storage). */
+const char* pm_last_error_detail(void);
+/* Library version string. */
+const char* pm_version(void);
+
+/* ------------------------------------------------------------------------ *
+ * Text encoding -- Sect. 2.1, Table 1: A,C,G,T -> 00,01,10,11.
+ *
+ * Device layout ("planar 2-bit"): the text is cut into blocks of 32 bases;
+ * block b is two 32-bit words, word 2b holding the high code bit of bases
+ * 32b..32b+31 (bit i <-> base 32b+i) and word 2b+1 the low code bit.  That
+ * is 8 bytes per 32 bases; a tail of zero blocks pads the buffer so that the
+ * kernels may read whole 16-byte groups past the last base.
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the encoded text buffer for n bases (including the padding). */
+uint64_t pm_text_bytes(uint64_t n);
+
+/* Encode n ASCII bases (A, C, G, T in either case) from ascii_dev into
+ * text_dev (pm_text_bytes(n) bytes).  bad_index_dev (one uint64 on the device)
+ * receives the smallest index of a byte that is not a base, or UINT64_MAX if
+ * there is none; bases at bad positions are encoded as A.  Text positions past
+ * n are encoded as zero blocks.  Asynchronous on `stream`. */
+pm_status pm_encode_text(const uint8_t* ascii_dev, uint64_t n, void* text_dev,
+                         uint64_t* bad_index_dev, void* stream);
+
+/* ------------------------------------------------------------------------ *
+ * Pattern encoding -- Sect. 2.2, Table 2 (4-bit IUPAC class codes 0..15)
+ * and Sect. 2.3, Table 3 (the 64-entry pair dictionary).
+ * ------------------------------------------------------------------------ */
+
+/* Parse a pattern of IUPAC letters (ACGTMRWSYKVHDBN, either case), '-'
+ * (missing symbol, code 15, matches no base) and bracketed classes such as
+ * "[CGT]" (canonicalised to their IUPAC code).  Writes min(m, cap) codes to
+ * `codes` (host) and the pattern length to *m_out.  PM_ERR_SYMBOL on an
+ * unknown symbol, an empty "[]", '-' inside brackets or an unclosed bracket. */
+pm_status pm_encode_pattern(const char* pattern, uint64_t len, uint8_t* codes, uint64_t cap,
+                            uint32_t* m_out);
+
+/* Fill table[64] (host) with the pair dictionary L of Table 3, index
+ * (p << 2) | t, value 0 for a match and 1 for a mismatch.  The values are
+ * derived from prime coding: base t gets prime q_t of (2, 3, 5, 7), class p
+ * the product of its members' primes (1 for '-'), and L = [q_t does not
+ * divide that product]. */
+pm_status pm_pair_table(uint8_t table[64]);
+
+/* Bytes of the device pattern image for a pattern of length m. */
+uint64_t pm_pattern_bytes(uint32_t m);
+
+/* Build the device pattern image on the host (image_host, `bytes` >=
+ * pm_pattern_bytes(m)); the caller copies it to device memory and passes it
+ * to pm_scan.  Layout: for each 32-position chunk c, four uint32 words, word
+ * 4c+t having bit j set iff text code t mismatches pattern position 32c+j
+ * (the Table 3 value of that pair); bits past m are 0. */
+pm_status pm_pattern_image(const uint8_t* codes, uint32_t m, void* image_host, uint64_t bytes);
+
+/* ------------------------------------------------------------------------ *
+ * Scan -- eq. (4) with the early stop of Sect. 2.4 and the text tiling of
+ * Sect. 2.6, for one pattern.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes pm_scan needs for a text of n bases (any m). */
+uint64_t pm_scan_workspace_bytes(uint64_t n);
+
+/* Scan windows [win_begin, win_end) (clipped to [0, n-m+1)) of the encoded
+ * text (n bases) against the pattern (host `codes`, m of them, and its device
+ * image from pm_pattern_image) with at most k mismatches (k <= 65535).
+ * Writes the hits in ascending position order: the first `capacity` of them
+ * to pos_dev (int64) and cnt_dev (uint16, the exact mismatch count, <= k);
+ * *n_hits_dev (device uint64) receives the total number of hits, which may
+ * exceed capacity (then the call can be repeated with a larger buffer).
+ * ws_dev: device workspace of at least pm_scan_workspace_bytes(n) bytes,
+ * overwritten.  m > n gives 0 hits.  Asynchronous on `stream`. */
+pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m,
+                  uint32_t k, const void* image_dev, uint64_t win_begin, uint64_t win_end,
+                  int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
+                  void* ws_dev, uint64_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMSCAN_H */

@@ -1,0 +1,61 @@
+// plan.hpp -- host-side pattern encoding and scan planning (private to
+// libpmscan).  Shared between the host code and the kernels: only the plain
+// structs below, which travel to the GPU as kernel arguments.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pm {
+
+// Filter slots are evaluated in groups of 8 and there are at most 64.
+constexpr int kMaxSlots = 64;
+// Threads per workgroup of the scan kernels.
+constexpr int kThreads = 256;
+
+// A filter slot packs (mismatch mask | q << 4 | r << 5): the 4-bit Table 3 row
+// of the position's class (bit t set <=> text code t mismatches), and the
+// position's offset from the filter window start as word q (0/1) and bit r.
+// Slot value 0 is an empty slot (never mismatches).
+struct ScanPlan {
+    uint32_t m;          // pattern length
+    uint32_t k;          // mismatch budget
+    int32_t keff;        // k minus the '-' positions (they always mismatch)
+    uint32_t n_dash;     // number of '-' positions
+    uint32_t n_slots;    // filter slots used (multiple of 8; 0 = no filter)
+    uint32_t levels;     // bit-sliced counter levels L, 2^L >= keff + 1
+    uint32_t init;       // counter start value 2^L - (keff + 1)
+    uint32_t exhaustive; // the slots hold every countable position
+    uint32_t fword;      // filter window start, in 32-base blocks (even)
+    uint32_t nchunks;    // ceil(m / 32): chunks of the pattern image
+    uint32_t singles;    // bit s set: singleton plane s (A,C,G,T) is used
+    uint32_t pad_;
+    uint16_t slot[kMaxSlots];
+};
+
+struct PatternInfo {
+    std::vector<uint8_t> codes;  // Table 2 codes
+};
+
+// Table 2: IUPAC letter -> code, or -1.
+int code_of_letter(char c);
+// Member text codes of a pattern code as a 4-bit set (bit t <=> Table 1 code t).
+unsigned members_of_code(unsigned code);
+// Product of the primes (2, 3, 5, 7) of the members; 1 for the empty class.
+uint32_t prime_product(unsigned code);
+// Table 3 row: bit t set <=> q_t does not divide prime_product(code).
+unsigned mismatch_mask(unsigned code);
+
+// Parse an IUPAC pattern with [..] classes.  Returns 0 or a negative pm_status;
+// `err` describes a failure.
+int parse_pattern(const char* s, uint64_t len, std::vector<uint8_t>& codes, std::string& err);
+
+// Pattern image for the verification pass: 4 words per 32 positions.
+void build_image(const uint8_t* codes, uint32_t m, uint32_t* out);
+inline uint64_t image_words(uint32_t m) { return 4ull * ((m + 31) / 32); }
+
+// Filter plan for (pattern, k).  `survival` is the target probability that a
+// random window survives the filter.
+ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival = 1e-5);
+
+}  // namespace pm
