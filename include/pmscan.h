@@ -119,8 +119,10 @@ uint64_t pm_scan_workspace_bytes(uint64_t n);
  * to pos_dev (int64) and cnt_dev (uint16, the exact mismatch count, <= k);
  * *n_hits_dev (device uint64) receives the total number of hits, which may
  * exceed capacity (then the call can be repeated with a larger buffer).
- * ws_dev: device workspace of at least pm_scan_workspace_bytes(n) bytes,
- * overwritten.  m > n gives 0 hits.  Asynchronous on `stream`. */
+ * ws_dev: device workspace of at least pm_scan_workspace_bytes(n) bytes; it
+ * needs no initialisation, holds nothing between calls, and must not be used
+ * by two calls that can run at the same time.  m > n gives 0 hits.
+ * Asynchronous on `stream`. */
 pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m,
                   uint32_t k, const void* image_dev, uint64_t win_begin, uint64_t win_end,
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,

@@ -137,80 +137,88 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
     // Positions that can mismatch and can also match ("countable").
     auto countable = [&](uint32_t j) { return mm[j] != 0u && mm[j] != 15u; };
     auto bits = [](unsigned x) { return __builtin_popcount(x); };
-    // Information of a position: log2(4 / |class|); mismatch probability for
-    // a uniform base: |mismatching bases| / 4.
-    auto info = [&](uint32_t j) { return std::log2(4.0 / (4 - bits(mm[j]))); };
-
-    // Filter window: 64 positions starting at an even block, holding the most
-    // information.
-    uint32_t best_fw = 0;
-    double best = -1.0;
-    for (uint32_t fw = 0; 32 * fw < m; fw += 2) {
-        double s = 0;
-        for (uint32_t j = 32 * fw; j < std::min(m, 32 * fw + 64); ++j)
-            if (countable(j)) s += info(j);
-        if (s > best + 1e-12) {
-            best = s;
-            best_fw = fw;
-        }
-    }
-    std::vector<uint32_t> cand;
+    // Two filters (both exact: a window they drop has more than keff
+    // mismatches among their slots alone):
+    //  - singleton filter: singleton positions of the 64-position window with
+    //    the most of them, a multiple of 8, just enough that few windows
+    //    survive; survivors are then counted over the whole pattern;
+    //  - exhaustive filter: every countable position, when they all lie in
+    //    one 64-position window; its counts are the exact window counts.
+    auto is_single = [&](uint32_t j) { return bits(mm[j]) == 3; };
     uint32_t n_countable = 0;
     for (uint32_t j = 0; j < m; ++j)
         if (countable(j)) ++n_countable;
-    for (uint32_t j = 32 * best_fw; j < std::min(m, 32 * best_fw + 64); ++j)
-        if (countable(j)) cand.push_back(j);
-    std::stable_sort(cand.begin(), cand.end(),
-                     [&](uint32_t a, uint32_t b) { return bits(mm[a]) > bits(mm[b]); });
-    const bool can_exhaust = cand.size() == n_countable;
+    uint32_t best_fw = 0, best_single = 0;
+    for (uint32_t fw = 0; 32 * fw < m; fw += 2) {
+        uint32_t c = 0;
+        for (uint32_t j = 32 * fw; j < std::min(m, 32 * fw + 64); ++j)
+            if (is_single(j)) ++c;
+        if (c > best_single) {
+            best_single = c;
+            best_fw = fw;
+        }
+    }
+    // exhaustive window: the first even block at or below the first countable position
+    uint32_t first = m, last = 0;
+    for (uint32_t j = 0; j < m; ++j)
+        if (countable(j)) {
+            first = std::min(first, j);
+            last = j;
+        }
+    const uint32_t ex_fw = n_countable ? (first / 32) & ~1u : 0;
+    const bool can_exhaust = n_countable == 0 || last < 32 * ex_fw + 64;
 
-    auto surv = [&](size_t J) {
-        // P(mismatches among the first J candidates <= keff), uniform bases.
+    // survival of a random window (uniform bases) for J singleton slots
+    auto surv_single = [&](uint32_t J) {
         std::vector<double> d(K + 1, 0.0);
         d[0] = 1.0;
-        for (size_t s = 0; s < std::min(J, cand.size()); ++s) {
-            const double q = bits(mm[cand[s]]) / 4.0;
+        for (uint32_t s = 0; s < J; ++s)
             for (int c = static_cast<int>(K); c >= 0; --c)
-                d[c] = d[c] * (1.0 - q) + (c > 0 ? d[c - 1] * q : 0.0);
-        }
+                d[c] = d[c] * 0.25 + (c > 0 ? d[c - 1] * 0.75 : 0.0);
         double tot = 0;
         for (uint32_t c = 0; c < K; ++c) tot += d[c];
         return tot;
     };
-
-    size_t J = 0;
-    bool exhaustive = false;
-    if (K > 64) {
-        exhaustive = n_countable == 0;
-    } else {
-        const size_t jmax = (cand.size() + 7) / 8 * 8;
+    uint32_t J = 0;
+    if (K <= 64) {
+        const uint32_t jmax = std::min<uint32_t>(best_single / 8 * 8, kMaxSlots);
         for (J = 8; J < jmax; J += 8)
-            if (surv(J) <= survival) break;
+            if (surv_single(J) <= survival) break;
         if (J > jmax) J = jmax;
-        if (can_exhaust && (cand.size() <= J + 16 || surv(J) > survival)) {
-            J = jmax;
-            exhaustive = true;
-        }
     }
+    const bool weak = J == 0 || surv_single(J) > survival;
+    if (can_exhaust && K <= 64 && (weak || n_countable <= J + 16)) {
+        // exhaustive filter
+        uint32_t L = 0;
+        while ((1u << L) < K) ++L;
+        p.levels = L;
+        p.init = (1u << L) - K;
+        p.exhaustive = 1;
+        p.fword = ex_fw;
+        p.n_slots = (n_countable + 7) / 8 * 8;
+        uint32_t s = 0;
+        for (uint32_t j = 0; j < m; ++j)
+            if (countable(j)) {
+                const uint32_t rel = j - 32 * ex_fw;
+                p.slot[s++] = static_cast<uint16_t>(mm[j] | ((rel >> 5) << 4) | ((rel & 31u) << 5));
+            }
+        return p;
+    }
+    p.exhaustive = 0;
+    p.fword = best_fw;
+    p.n_slots = J;
     if (J > 0) {
         uint32_t L = 0;
         while ((1u << L) < K) ++L;
         p.levels = L;
         p.init = (1u << L) - K;
-    }
-    p.exhaustive = exhaustive ? 1u : 0u;
-    p.fword = best_fw;
-    p.n_slots = static_cast<uint32_t>(J);
-    for (size_t s = 0; s < J && s < cand.size(); ++s) {
-        const uint32_t rel = cand[s] - 32 * best_fw;
-        const unsigned x = mm[cand[s]];
-        p.slot[s] = static_cast<uint16_t>(x | ((rel >> 5) << 4) | ((rel & 31u) << 5));
-        switch (x) {
-            case 14u: p.singles |= 1u; break;  // A
-            case 13u: p.singles |= 2u; break;  // C
-            case 11u: p.singles |= 4u; break;  // G
-            case 7u: p.singles |= 8u; break;   // T
-            default: break;
+        uint32_t s = 0;
+        for (uint32_t j = 32 * best_fw; j < std::min(m, 32 * best_fw + 64) && s < J; ++j) {
+            if (!is_single(j)) continue;
+            const uint32_t rel = j - 32 * best_fw;
+            const unsigned base = static_cast<unsigned>(__builtin_ctz(~mm[j] & 15u));
+            p.slot[s++] = static_cast<uint16_t>(base | ((rel >> 5) << 2) | ((rel & 31u) << 3));
+            p.singles |= 1u << base;
         }
     }
     return p;

@@ -13,10 +13,13 @@ constexpr int kMaxSlots = 64;
 // Threads per workgroup of the scan kernels.
 constexpr int kThreads = 256;
 
-// A filter slot packs (mismatch mask | q << 4 | r << 5): the 4-bit Table 3 row
-// of the position's class (bit t set <=> text code t mismatches), and the
-// position's offset from the filter window start as word q (0/1) and bit r.
-// Slot value 0 is an empty slot (never mismatches).
+// A filter slot is one pattern position inside the 64-position filter window,
+// at offset 32*q + r from its start (q = 0 or 1).
+//  - singleton filter (exhaustive = 0): slot = c | q << 2 | r << 3, c the
+//    position's base (Table 1 code); the slot count is a multiple of 8.
+//  - exhaustive filter (exhaustive = 1): slot = mm | q << 4 | r << 5, mm the
+//    position's Table 3 row (bit t set <=> text code t mismatches); mm = 0
+//    pads the last group of 8 and never mismatches.
 struct ScanPlan {
     uint32_t m;          // pattern length
     uint32_t k;          // mismatch budget
@@ -25,10 +28,10 @@ struct ScanPlan {
     uint32_t n_slots;    // filter slots used (multiple of 8; 0 = no filter)
     uint32_t levels;     // bit-sliced counter levels L, 2^L >= keff + 1
     uint32_t init;       // counter start value 2^L - (keff + 1)
-    uint32_t exhaustive; // the slots hold every countable position
+    uint32_t exhaustive; // the slots hold every countable position (exact counts)
     uint32_t fword;      // filter window start, in 32-base blocks (even)
     uint32_t nchunks;    // ceil(m / 32): chunks of the pattern image
-    uint32_t singles;    // bit s set: singleton plane s (A,C,G,T) is used
+    uint32_t singles;    // bit c set: the singleton plane of base c is used
     uint32_t pad_;
     uint16_t slot[kMaxSlots];
 };
@@ -55,7 +58,8 @@ void build_image(const uint8_t* codes, uint32_t m, uint32_t* out);
 inline uint64_t image_words(uint32_t m) { return 4ull * ((m + 31) / 32); }
 
 // Filter plan for (pattern, k).  `survival` is the target probability that a
-// random window survives the filter.
-ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival = 1e-5);
+// random window survives the filter (survivors are counted exactly one by
+// one, so a few per 16K windows cost little).
+ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival = 4e-5);
 
 }  // namespace pm

@@ -16,9 +16,13 @@
 //   2. verify: windows that survive are counted exactly over all m positions
 //      (one window per lane, 32 positions per step) unless the slots already
 //      covered every position that can mismatch.
-//   3. output: hits are compacted in position order with a workgroup prefix
-//      sum, and tiles are chained in order by a decoupled look-back over a
-//      per-tile status word, so the output list is ascending without a sort.
+//   3. output: a tile is the 64*R*32 windows of one wave; the wave ranks its
+//      hits with a prefix sum over its lanes and stores their number and, when
+//      there are at most kCap, the hits themselves.  A second kernel sums the
+//      counts per chunk of tiles, and a third places every tile's hits at their
+//      ordered offset (re-scanning only tiles that had more than kCap hits).
+//      Waves never wait on each other, and the output list is ascending
+//      without a sort.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -144,6 +148,9 @@ __global__ void encode_text_kernel(const uint8_t* __restrict__ ascii, uint64_t n
 // scan
 // ---------------------------------------------------------------------------
 
+constexpr int kCap = 32;      // hits a tile stages for the placement kernel
+constexpr int kChunk = 1024;  // tiles per chunk of the hit-count prefix
+
 struct ScanArgs {
     const uint4* text4;        // encoded text as 16-byte groups (two blocks each)
     uint64_t n4;               // 16-byte groups in the buffer
@@ -154,9 +161,10 @@ struct ScanArgs {
     uint16_t* cnt;
     uint64_t capacity;
     unsigned long long* n_hits;
-    unsigned long long* status;  // per-tile look-back words
-    uint32_t* tile_counter;
-    uint32_t n_tiles;
+    uint32_t* counts;                // hits per tile
+    unsigned long long* chunk_sum;   // hits per chunk of kChunk tiles
+    unsigned long long* staged;      // kCap per tile: (window offset << 16) | count
+    uint32_t n_tiles, n_chunks;
 };
 
 // Mismatch word of 32 windows for one pattern position, from the text's high
@@ -178,49 +186,66 @@ __device__ __forceinline__ uint32_t align(uint32_t hi, uint32_t lo, uint32_t r) 
 
 template <int R>
 struct Lane {
-    uint32_t h[R + 2], l[R + 2];           // raw planes of blocks B+fw .. B+fw+R+1
-    uint32_t pa[R + 2], pc[R + 2], pg[R + 2], pt[R + 2];  // singleton mismatch planes
+    uint32_t h[R + 2], l[R + 2];  // raw planes of blocks B+fw .. B+fw+R+1
+    uint32_t P[4][R + 2];          // P[c]: mismatch plane of singleton base c
 };
 
-// Mismatch words X[i] (lane word i) of one filter slot: position offset
-// 32*Q + r from the filter window start, Table 3 row MM.
-template <unsigned MM, int Q, int R>
-__device__ __forceinline__ void slot_words(const Lane<R>& s, uint32_t r, uint32_t (&X)[R]) {
+// Singleton-filter slot (c | q << 2 | r << 3): mismatch words of the 32*R
+// windows of the lane for the position 32*q + r of the filter window whose
+// class is the single base c.  The dispatch over (c, q) is uniform.
+template <int C, int Q, int R>
+__device__ __forceinline__ void single_words(const Lane<R>& s, uint32_t r, uint32_t (&X)[R]) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) X[i] = align(s.P[C][i + Q + 1], s.P[C][i + Q], r);
+}
+
+template <int R>
+__device__ __forceinline__ void single_slot(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
+    const uint32_t r = slot >> 3;
+    switch (slot & 7u) {
+        case 0: single_words<0, 0, R>(s, r, X); break;
+        case 1: single_words<1, 0, R>(s, r, X); break;
+        case 2: single_words<2, 0, R>(s, r, X); break;
+        case 3: single_words<3, 0, R>(s, r, X); break;
+        case 4: single_words<0, 1, R>(s, r, X); break;
+        case 5: single_words<1, 1, R>(s, r, X); break;
+        case 6: single_words<2, 1, R>(s, r, X); break;
+        default: single_words<3, 1, R>(s, r, X); break;
+    }
+}
+
+// Exhaustive-filter slot (mm | q << 4 | r << 5): any class, its Table 3 row
+// mm applied to the shifted planes without branching on it.
+template <int Q, int R>
+__device__ __forceinline__ void general_words(const Lane<R>& s, uint32_t r, uint32_t mA, uint32_t mC,
+                                              uint32_t mG, uint32_t mT, uint32_t (&X)[R]) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        if constexpr (MM == 14u) X[i] = align(s.pa[i + Q + 1], s.pa[i + Q], r);
-        else if constexpr (MM == 13u) X[i] = align(s.pc[i + Q + 1], s.pc[i + Q], r);
-        else if constexpr (MM == 11u) X[i] = align(s.pg[i + Q + 1], s.pg[i + Q], r);
-        else if constexpr (MM == 7u) X[i] = align(s.pt[i + Q + 1], s.pt[i + Q], r);
-        else if constexpr (MM == 12u) X[i] = align(s.h[i + Q + 1], s.h[i + Q], r);  // [AC]
-        else if constexpr (MM == 10u) X[i] = align(s.l[i + Q + 1], s.l[i + Q], r);  // [AG]
-        else {
-            const uint32_t H = align(s.h[i + Q + 1], s.h[i + Q], r);
-            const uint32_t L = align(s.l[i + Q + 1], s.l[i + Q], r);
-            X[i] = mismatch_fn<MM>(H, L);
-        }
+        const uint32_t H = align(s.h[i + Q + 1], s.h[i + Q], r);
+        const uint32_t L = align(s.l[i + Q + 1], s.l[i + Q], r);
+        X[i] = (H & ((L & mT) | (~L & mG))) | (~H & ((L & mC) | (~L & mA)));
     }
 }
 
 template <int R>
-__device__ __forceinline__ void slot_dispatch(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
+__device__ __forceinline__ void general_slot(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
     const uint32_t r = slot >> 5;
-    switch (slot & 31u) {
-#define PM_CASE(MM)                                  \
-    case MM: slot_words<MM, 0, R>(s, r, X); break;   \
-    case MM + 16: slot_words<MM, 1, R>(s, r, X); break;
-        PM_CASE(1) PM_CASE(2) PM_CASE(3) PM_CASE(4) PM_CASE(5) PM_CASE(6) PM_CASE(7)
-        PM_CASE(8) PM_CASE(9) PM_CASE(10) PM_CASE(11) PM_CASE(12) PM_CASE(13) PM_CASE(14)
-#undef PM_CASE
-        default:
-#pragma unroll
-            for (int i = 0; i < R; ++i) X[i] = 0u;
-            break;
-    }
+    const uint32_t mA = 0u - (slot & 1u), mC = 0u - (slot >> 1 & 1u);
+    const uint32_t mG = 0u - (slot >> 2 & 1u), mT = 0u - (slot >> 3 & 1u);
+    if (slot & 16u) general_words<1, R>(s, r, mA, mC, mG, mT, X);
+    else general_words<0, R>(s, r, mA, mC, mG, mT, X);
 }
 
+// Full-adder halves as single three-input LUT operations (v_bitop3_b32);
+// both functions are symmetric in their inputs.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
 __device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
-    return (a & b) | (a & c) | (b & c);
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
+}
+__device__ __forceinline__ uint32_t or3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE);
 }
 
 // Bit-sliced counters: S[l][i] is bit l of the counts of the 32 windows of
@@ -240,12 +265,12 @@ __device__ __forceinline__ void add2(Counters<R, L>& c, const uint32_t (&a)[R], 
                                      uint32_t (&out)[R]) {
     if constexpr (LV == L) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) c.dead[i] |= a[i] | b[i];
+        for (int i = 0; i < R; ++i) c.dead[i] = or3(c.dead[i], a[i], b[i]);
     } else if constexpr (LV < L) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             const uint32_t s = c.S[LV][i];
-            c.S[LV][i] = s ^ a[i] ^ b[i];
+            c.S[LV][i] = xor3(s, a[i], b[i]);
             out[i] = maj3(s, a[i], b[i]);
         }
     }
@@ -288,27 +313,55 @@ __device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* _
     return cnt;
 }
 
-template <int R, int L>
-__global__ __launch_bounds__(TPB) void scan_kernel(ScanArgs a, ScanPlan p) {
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_wave_sum[TPB / 64];
-    __shared__ unsigned long long s_base;
+// Filter + verification of one tile: hit[i] gets the windows of lane word i
+// (32*(B+i) + bit) with at most k mismatches; C keeps the filter counters
+// (exact counts when the plan is exhaustive).
+// The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
+// (B and fw are even).  Lanes past the end of the text read the last group.
+template <int R>
+__device__ __forceinline__ void load_text(const ScanArgs& a, const ScanPlan& p, uint64_t B,
+                                          uint4 (&t)[(R + 2) / 2]) {
+    const uint64_t g0 = (B + p.fword) >> 1;
+#pragma unroll
+    for (int u = 0; u < (R + 2) / 2; ++u) {
+        uint64_t gi = g0 + u;
+        if (gi >= a.n4) gi = a.n4 - 1;
+        t[u] = a.text4[gi];
+    }
+}
 
-    if (threadIdx.x == 0) s_tile = atomicAdd(a.tile_counter, 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint64_t B = a.wb0 + (uint64_t)tile * (TPB * R) + (uint64_t)threadIdx.x * R;
+// The same for a whole tile starting at block T0 (wave-uniform): tiles that
+// end before the last 16-byte group need no clamping.
+template <int R>
+__device__ __forceinline__ void load_tile_text(const ScanArgs& a, const ScanPlan& p, uint64_t T0,
+                                               uint4 (&t)[(R + 2) / 2]) {
+    // group indices fit in 32 bits (texts below 2^37 bases); clamping is one
+    // v_min per load and only changes anything in the last tile
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t g0 = (uint32_t)((T0 + p.fword) >> 1) + lane * (R / 2);
+    const uint32_t last = (uint32_t)(a.n4 - 1);
+#pragma unroll
+    for (int u = 0; u < (R + 2) / 2; ++u) t[u] = a.text4[min(g0 + (uint32_t)u, last)];
+}
 
+template <int R, int L, bool EXH>
+__device__ __forceinline__ void tile_hits(const ScanArgs& a, const ScanPlan& p, uint64_t B, bool interior,
+                                          const uint4 (&t)[(R + 2) / 2], Counters<R, L>& C,
+                                          uint32_t (&hit)[R], uint32_t& nh) {
     // ---- valid windows of each lane word ------------------------------------
-    Counters<R, L> C;
+    // (windows outside [win_begin, win_end) start dead; `interior` says the
+    // whole tile lies inside, which holds for all tiles but the edge ones)
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const uint64_t w0 = 32 * (B + i);
-        uint32_t valid = 0;
-        if (w0 < a.win_end && w0 + 32 > a.win_begin) {
-            const uint32_t lo = a.win_begin > w0 ? (uint32_t)(a.win_begin - w0) : 0u;
-            const uint32_t hi = a.win_end < w0 + 32 ? (uint32_t)(a.win_end - w0) : 32u;
-            valid = (hi == 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        uint32_t valid = ~0u;
+        if (!interior) {
+            const uint64_t w0 = 32 * (B + i);
+            valid = 0;
+            if (w0 < a.win_end && w0 + 32 > a.win_begin) {
+                const uint32_t lo = a.win_begin > w0 ? (uint32_t)(a.win_begin - w0) : 0u;
+                const uint32_t hi = a.win_end < w0 + 32 ? (uint32_t)(a.win_end - w0) : 32u;
+                valid = (hi == 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+            }
         }
         C.dead[i] = ~valid;
         if constexpr (L > 0) {
@@ -320,46 +373,48 @@ __global__ __launch_bounds__(TPB) void scan_kernel(ScanArgs a, ScanPlan p) {
     // ---- filter ---------------------------------------------------------------
     if (p.n_slots > 0) {
         Lane<R> s;
-        const uint64_t g0 = (B + p.fword) >> 1;
 #pragma unroll
         for (int u = 0; u < (R + 2) / 2; ++u) {
-            uint64_t gi = g0 + u;
-            if (gi >= a.n4) gi = a.n4 - 1;  // lanes past the text: values unused
-            const uint4 v = a.text4[gi];
-            s.h[2 * u] = v.x;
-            s.l[2 * u] = v.y;
-            s.h[2 * u + 1] = v.z;
-            s.l[2 * u + 1] = v.w;
+            s.h[2 * u] = t[u].x;
+            s.l[2 * u] = t[u].y;
+            s.h[2 * u + 1] = t[u].z;
+            s.l[2 * u + 1] = t[u].w;
         }
-        if (p.singles & 1u) {
+        if constexpr (!EXH) {
 #pragma unroll
-            for (int w = 0; w < R + 2; ++w) s.pa[w] = mismatch_fn<14u>(s.h[w], s.l[w]);
-        }
-        if (p.singles & 2u) {
+            for (int c = 0; c < 4; ++c) {
+                if (p.singles >> c & 1u) {
 #pragma unroll
-            for (int w = 0; w < R + 2; ++w) s.pc[w] = mismatch_fn<13u>(s.h[w], s.l[w]);
-        }
-        if (p.singles & 4u) {
-#pragma unroll
-            for (int w = 0; w < R + 2; ++w) s.pg[w] = mismatch_fn<11u>(s.h[w], s.l[w]);
-        }
-        if (p.singles & 8u) {
-#pragma unroll
-            for (int w = 0; w < R + 2; ++w) s.pt[w] = mismatch_fn<7u>(s.h[w], s.l[w]);
+                    for (int w = 0; w < R + 2; ++w) {
+                        // mismatch with base c: the text code differs from c
+                        const uint32_t hx = (c & 2) ? ~s.h[w] : s.h[w];
+                        const uint32_t lx = (c & 1) ? ~s.l[w] : s.l[w];
+                        s.P[c][w] = hx | lx;
+                    }
+                }
+            }
         }
 
+        const uint4* groups = reinterpret_cast<const uint4*>(p.slot);  // 8 slots per 16 bytes
         for (uint32_t g = 0; g < p.n_slots; g += 8) {
+            const uint4 gw = groups[g >> 3];
+            const uint32_t gv[4] = {gw.x, gw.y, gw.z, gw.w};
             uint32_t xa[R], xb[R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
 #pragma unroll
                 for (int pr = 0; pr < 2; ++pr) {
-                    const int u = 4 * half + 2 * pr;
-                    slot_dispatch<R>(p.slot[g + u], s, xa);
-                    slot_dispatch<R>(p.slot[g + u + 1], s, xb);
+                    const uint32_t w = gv[2 * half + pr];  // slots u and u+1
+                    if constexpr (EXH) {
+                        general_slot<R>(w & 0xFFFFu, s, xa);
+                        general_slot<R>(w >> 16, s, xb);
+                    } else {
+                        single_slot<R>(w & 0xFFFFu, s, xa);
+                        single_slot<R>(w >> 16, s, xb);
+                    }
                     if constexpr (L == 0) {
 #pragma unroll
-                        for (int i = 0; i < R; ++i) C.dead[i] |= xa[i] | xb[i];
+                        for (int i = 0; i < R; ++i) C.dead[i] = or3(C.dead[i], xa[i], xb[i]);
                     } else {
                         add2<0, R, L>(C, xa, xb, pr == 0 ? c0a : c0b);
                     }
@@ -372,15 +427,22 @@ __global__ __launch_bounds__(TPB) void scan_kernel(ScanArgs a, ScanPlan p) {
     }
 
     // ---- survivors -> hits -----------------------------------------------------
-    uint32_t hit[R];
-    uint32_t nh = 0;
-    if (p.exhaustive) {
+    nh = 0;
+    if constexpr (EXH) {
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             hit[i] = ~C.dead[i];
             nh += __builtin_popcount(hit[i]);
         }
     } else {
+        uint32_t any = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) any |= ~C.dead[i];
+        if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
+#pragma unroll
+            for (int i = 0; i < R; ++i) hit[i] = 0;
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             uint32_t alive = ~C.dead[i];
@@ -395,56 +457,27 @@ __global__ __launch_bounds__(TPB) void scan_kernel(ScanArgs a, ScanPlan p) {
             nh += __builtin_popcount(h);
         }
     }
+}
 
-    // ---- ordered compaction: workgroup scan + decoupled look-back ---------------
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    uint32_t incl = nh;
+// Exact count of hit window `b` of lane word i.
+template <int R, int L, bool EXH>
+__device__ __forceinline__ uint32_t hit_count(const ScanArgs& a, const ScanPlan& p, const Counters<R, L>& C,
+                                              int i, uint32_t b, uint64_t pos) {
+    if constexpr (EXH) {
+        uint32_t v = 0;
+        if constexpr (L > 0) {
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t v = __shfl_up(incl, d, 64);
-        if (lane >= (uint32_t)d) incl += v;
-    }
-    if (lane == 63) s_wave_sum[wave] = incl;
-    __syncthreads();
-    uint32_t wave_off = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < TPB / 64; ++w) {
-        const uint32_t v = s_wave_sum[w];
-        if ((uint32_t)w < wave) wave_off += v;
-        total += v;
-    }
-    if (threadIdx.x == 0) {
-        unsigned long long excl = 0;
-        if (tile == 0) {
-            __hip_atomic_store(&a.status[0], ((unsigned long long)total << 2) | 2ull, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            __hip_atomic_store(&a.status[tile], ((unsigned long long)total << 2) | 1ull,
-                               __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            // Every tile publishes its own total before looking back, and tiles
-            // with smaller ids started earlier, so each wait below ends.
-            uint32_t j = tile - 1;
-            while (true) {
-                const unsigned long long v =
-                    __hip_atomic_load(&a.status[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                const unsigned flag = (unsigned)(v & 3ull);
-                if (flag == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += v >> 2;
-                if (flag == 2) break;
-                --j;
-            }
-            __hip_atomic_store(&a.status[tile], ((excl + total) << 2) | 2ull, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            for (int l = 0; l < L; ++l) v |= (C.S[l][i] >> b & 1u) << l;
         }
-        if (tile == a.n_tiles - 1) *a.n_hits = excl + total;
-        s_base = excl;
+        return v - p.init + p.n_dash;
     }
-    __syncthreads();
-    if (nh == 0) return;
-    unsigned long long idx = s_base + wave_off + (incl - nh);
+    return count_window(a.text4, a.image, p.nchunks, pos, p.k);
+}
+
+// Write the hits of this lane, in order, starting at output index `idx`.
+template <int R, int L, bool EXH>
+__device__ __forceinline__ void write_hits(const ScanArgs& a, const ScanPlan& p, const Counters<R, L>& C,
+                                           const uint32_t (&hit)[R], uint64_t B, unsigned long long idx) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
         uint32_t h = hit[i];
@@ -453,53 +486,245 @@ __global__ __launch_bounds__(TPB) void scan_kernel(ScanArgs a, ScanPlan p) {
             h &= h - 1u;
             if (idx < a.capacity) {
                 const uint64_t pos = 32 * (B + i) + b;
-                uint32_t c;
-                if (p.exhaustive) {
-                    uint32_t v = 0;
-                    if constexpr (L > 0) {
-#pragma unroll
-                        for (int l = 0; l < L; ++l) v |= (C.S[l][i] >> b & 1u) << l;
-                    }
-                    c = v - p.init + p.n_dash;
-                } else {
-                    c = count_window(a.text4, a.image, p.nchunks, pos, p.k);
-                }
                 a.pos[idx] = (int64_t)pos;
-                a.cnt[idx] = (uint16_t)c;
+                a.cnt[idx] = (uint16_t)hit_count<R, L, EXH>(a, p, C, i, b, pos);
             }
             ++idx;
         }
     }
 }
 
-constexpr int kR = 8;  // lane words per lane
+// A tile is the 64 lanes of one wave, R lane words (32 windows) each.
+__device__ __forceinline__ uint64_t tile_first_block(const ScanArgs& a, uint32_t tile, int R) {
+    return a.wb0 + (uint64_t)tile * (uint64_t)(64 * R);
+}
 
-using ScanFn = void (*)(ScanArgs, ScanPlan);
-template <int R>
-ScanFn pick_scan(uint32_t L) {
-    switch (L) {
-        case 0: return scan_kernel<R, 0>;
-        case 1: return scan_kernel<R, 1>;
-        case 2: return scan_kernel<R, 2>;
-        case 3: return scan_kernel<R, 3>;
-        case 4: return scan_kernel<R, 4>;
-        case 5: return scan_kernel<R, 5>;
-        case 6: return scan_kernel<R, 6>;
-        default: return nullptr;
+__device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint64_t T0, int R) {
+    return 32 * T0 >= a.win_begin && 32 * (T0 + 64 * (uint64_t)R) <= a.win_end;
+}
+
+// Exclusive prefix of `x` over the lanes of a wave; `total` gets the sum.
+__device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += v;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - x;
+}
+
+// Pass 1: every tile (one wave's windows) finds its hits, stores their number,
+// and stages them when there are at most kCap.  Waves are persistent and
+// independent: wave w takes tiles w, w + W, w + 2W, ... (W waves in the grid).
+template <int R, int L, bool EXH>
+__global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nw = gridDim.x * (TPB / 64);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+    for (uint32_t tile = blockIdx.x * (TPB / 64) + wave; tile < a.n_tiles; tile += nw) {
+        const uint64_t T0 = tile_first_block(a, tile, R);
+        const uint64_t B = T0 + (uint64_t)lane * R;
+        uint4 txt[(R + 2) / 2];
+        load_tile_text<R>(a, p, T0, txt);
+        Counters<R, L> C;
+        uint32_t hit[R], nh;
+        tile_hits<R, L, EXH>(a, p, B, tile_interior(a, T0, R), txt, C, hit, nh);
+        if (__ballot(nh != 0) == 0) {  // the usual case: no hits in the tile
+            if (lane == 0) a.counts[tile] = 0;
+            continue;
+        }
+        uint32_t total;
+        const uint32_t excl = wave_exclusive(nh, total);
+        if (lane == 0) a.counts[tile] = total;
+        if (total > (uint32_t)kCap || nh == 0) continue;
+        unsigned long long* out = a.staged + (uint64_t)tile * kCap + excl;
+        const uint64_t base = 32 * T0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            uint32_t h = hit[i];
+            while (h) {
+                const uint32_t b = __builtin_ctz(h);
+                h &= h - 1u;
+                const uint64_t pos = 32 * (B + i) + b;
+                const uint32_t c = hit_count<R, L, EXH>(a, p, C, i, b, pos);
+                *out++ = ((pos - base) << 16) | c;
+            }
+        }
     }
 }
 
-// blocks of an encoded text buffer: the text, then zero padding, rounded to
-// an even count so the buffer is a whole number of 16-byte groups
+// Pass 2: hits per chunk of kChunk tiles.
+__global__ __launch_bounds__(TPB) void chunk_sum_kernel(ScanArgs a) {
+    const uint64_t first = (uint64_t)blockIdx.x * kChunk;
+    unsigned long long v = 0;
+    for (uint32_t t = threadIdx.x; t < (uint32_t)kChunk; t += TPB)
+        if (first + t < a.n_tiles) v += a.counts[first + t];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __shared__ unsigned long long s[TPB / 64];
+    if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < TPB / 64; ++w) t += s[w];
+        a.chunk_sum[blockIdx.x] = t;
+    }
+}
+
+// Wave sum of x[first .. last) (all 64 lanes of one wave call it).
+template <typename T>
+__device__ __forceinline__ unsigned long long wave_sum(const T* x, uint64_t first, uint64_t last) {
+    const uint32_t lane = threadIdx.x & 63u;
+    unsigned long long v = 0;
+    for (uint64_t i = first + lane; i < last; i += 64) v += x[i];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Pass 3: each workgroup takes 64 consecutive tiles: one wave ranks their
+// hit counts, then every tile with hits has them placed at its ordered
+// offset -- copied from the staging area, or, for tiles with more than kCap
+// hits, found again by the whole workgroup and written directly.
+template <int R, int L, bool EXH>
+__global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p) {
+    __shared__ uint32_t s_count[64];
+    __shared__ unsigned long long s_prefix[64];
+    __shared__ unsigned long long s_busy;
+    const uint64_t t0 = (uint64_t)blockIdx.x * 64;
+    if (threadIdx.x < 64) {
+        const uint32_t lane = threadIdx.x;
+        if (blockIdx.x == 0) {
+            const unsigned long long all = wave_sum(a.chunk_sum, 0, a.n_chunks);
+            if (lane == 0) *a.n_hits = all;
+        }
+        const uint32_t count = t0 + lane < a.n_tiles ? a.counts[t0 + lane] : 0u;
+        const unsigned long long busy = __ballot(count != 0);
+        unsigned long long incl = count;
+        if (busy) {
+            // tiles before t0: whole chunks, then the rest of t0's chunk
+            const uint64_t c = t0 / kChunk;
+            const unsigned long long base = wave_sum(a.chunk_sum, 0, c) + wave_sum(a.counts, c * kChunk, t0);
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const unsigned long long v = __shfl_up(incl, d, 64);
+                if (lane >= (uint32_t)d) incl += v;
+            }
+            s_prefix[lane] = base + incl - count;
+        }
+        s_count[lane] = count;
+        if (lane == 0) s_busy = busy;
+    }
+    __syncthreads();
+    // staged tiles: the whole workgroup copies, tile after tile
+    unsigned long long busy = s_busy;
+    unsigned long long over = 0;  // tiles to scan again (more than kCap hits)
+    while (busy) {
+        const uint32_t l = __builtin_ctzll(busy);
+        busy &= busy - 1ull;
+        const uint32_t count = s_count[l];
+        const unsigned long long prefix = s_prefix[l];
+        if (prefix >= a.capacity) break;  // later tiles start even later
+        if (count > (uint32_t)kCap) {
+            over |= 1ull << l;
+            continue;
+        }
+        const uint32_t tile = (uint32_t)(t0 + l);
+        const uint64_t T0 = tile_first_block(a, tile, R);
+        const unsigned long long* src = a.staged + (uint64_t)tile * kCap;
+        for (uint32_t i = threadIdx.x; i < count; i += TPB) {
+            const unsigned long long v = src[i];
+            const unsigned long long dst = prefix + i;
+            if (dst < a.capacity) {
+                a.pos[dst] = (int64_t)(32 * T0 + (v >> 16));
+                a.cnt[dst] = (uint16_t)(v & 0xFFFFu);
+            }
+        }
+    }
+    // tiles with more than kCap hits: wave w scans every 4th of them again
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t j = 0; over; ++j) {
+        const uint32_t l = __builtin_ctzll(over);
+        over &= over - 1ull;
+        if (j % (TPB / 64) != wave) continue;
+        const uint32_t tile = (uint32_t)(t0 + l);
+        const uint64_t T0 = tile_first_block(a, tile, R);
+        const uint64_t B = T0 + (uint64_t)lane * R;
+        uint4 txt[(R + 2) / 2];
+        load_text<R>(a, p, B, txt);
+        Counters<R, L> C;
+        uint32_t hit[R], nh;
+        tile_hits<R, L, EXH>(a, p, B, tile_interior(a, T0, R), txt, C, hit, nh);
+        uint32_t total;
+        const uint32_t excl = wave_exclusive(nh, total);
+        if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, s_prefix[l] + excl);
+    }
+}
+
+#ifndef PMSCAN_LANE_WORDS
+#define PMSCAN_LANE_WORDS 6
+#endif
+constexpr int kR = PMSCAN_LANE_WORDS;  // lane words (32 windows each) per lane
+
+using ScanFn = void (*)(ScanArgs, ScanPlan);
+struct ScanPair {
+    ScanFn count, place;
+};
+template <int R, bool EXH>
+ScanPair pick_scan_l(uint32_t L) {
+    switch (L) {
+#define PM_L(X) case X: return {scan_count_kernel<R, X, EXH>, scan_place_kernel<R, X, EXH>};
+        PM_L(0) PM_L(1) PM_L(2) PM_L(3) PM_L(4) PM_L(5) PM_L(6)
+#undef PM_L
+        default: return {nullptr, nullptr};
+    }
+}
+template <int R>
+ScanPair pick_scan(const ScanPlan& p) {
+    return p.exhaustive ? pick_scan_l<R, true>(p.levels) : pick_scan_l<R, false>(p.levels);
+}
+
+// Workgroups for a persistent kernel: as many as fit on the device at once
+// (occupancy per CU x CUs), never more than there are tiles.
+unsigned persistent_grid(ScanFn fn, uint64_t n_tiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), TPB, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        cus = 256;
+        per_cu = 2;
+    }
+    return (unsigned)std::min<uint64_t>(n_tiles, (uint64_t)cus * (uint64_t)per_cu);
+}
+
 uint64_t text_blocks(uint64_t n) { return ((n + 31) / 32 + kPadBlocks + 1) & ~1ull; }
 
 uint64_t max_tiles(uint64_t n) {
-    // tiles of TPB*kR blocks, starting at an even block at or below win_begin
+    // tiles of 64*kR blocks, starting at an even block at or below win_begin
     const uint64_t blocks = (n + 31) / 32 + 2;
-    return (blocks + (uint64_t)TPB * kR - 1) / ((uint64_t)TPB * kR) + 1;
+    return (blocks + 64ull * kR - 1) / (64ull * kR) + 1;
 }
 
-constexpr uint64_t kWsHeader = 256;
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+// Workspace layout for up to T tiles: hit counts (u32 per tile), chunk sums
+// (u64 per kChunk tiles), staged hits (kCap u64 per tile).
+struct WsLayout {
+    uint64_t counts, chunk_sum, staged, bytes;
+};
+WsLayout ws_layout(uint64_t T) {
+    WsLayout w;
+    w.counts = 0;
+    w.chunk_sum = align256(4 * T);
+    w.staged = w.chunk_sum + align256(8 * ((T + kChunk - 1) / kChunk));
+    w.bytes = w.staged + 8 * (uint64_t)kCap * T;
+    return w;
+}
 
 }  // namespace
 
@@ -579,7 +804,7 @@ pm_status pm_pattern_image(const uint8_t* codes, uint32_t m, void* image_host, u
     return PM_OK;
 }
 
-uint64_t pm_scan_workspace_bytes(uint64_t n) { return kWsHeader + 8 * max_tiles(n); }
+uint64_t pm_scan_workspace_bytes(uint64_t n) { return ws_layout(max_tiles(n)).bytes; }
 
 pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m, uint32_t k,
                   const void* image_dev, uint64_t win_begin, uint64_t win_end, int64_t* pos_dev,
@@ -595,6 +820,7 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     if (reinterpret_cast<uintptr_t>(image_dev) % 16 != 0)
         return fail(PM_ERR_ARG, "image_dev must be 16-byte aligned");
     if (ws_bytes < pm_scan_workspace_bytes(n)) return fail(PM_ERR_WORKSPACE, "workspace too small");
+    if (text_blocks(n) / 2 >= (1ull << 32)) return fail(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
     for (uint32_t j = 0; j < m; ++j)
         if (codes[j] > 15) return fail(PM_ERR_SYMBOL, "pattern code above 15 at " + std::to_string(j));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -606,14 +832,15 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
 
     const uint64_t wb0 = (win_begin >> 5) & ~1ull;
     const uint64_t wb_end = (win_end + 31) >> 5;
-    const uint64_t tile_blocks = (uint64_t)TPB * kR;
+    const uint64_t tile_blocks = 64ull * kR;
     const uint64_t n_tiles = (wb_end - wb0 + tile_blocks - 1) / tile_blocks;
     if (n_tiles > max_tiles(n) || n_tiles > 0xFFFFFFFFull) return fail(PM_ERR_ARG, "window range too large");
 
-    ScanFn fn = pick_scan<kR>(plan.levels);
-    if (!fn) return fail(PM_ERR_UNSUPPORTED, "counter levels out of range");
+    const ScanPair fn = pick_scan<kR>(plan);
+    if (!fn.count) return fail(PM_ERR_UNSUPPORTED, "counter levels out of range");
 
     uint8_t* ws = reinterpret_cast<uint8_t*>(ws_dev);
+    const WsLayout lay = ws_layout(max_tiles(n));
     ScanArgs a;
     a.text4 = reinterpret_cast<const uint4*>(text_dev);
     a.n4 = text_blocks(n) / 2;
@@ -625,18 +852,17 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     a.cnt = cnt_dev;
     a.capacity = capacity;
     a.n_hits = reinterpret_cast<unsigned long long*>(n_hits_dev);
-    a.tile_counter = reinterpret_cast<uint32_t*>(ws);
-    a.status = reinterpret_cast<unsigned long long*>(ws + kWsHeader);
+    a.counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
+    a.chunk_sum = reinterpret_cast<unsigned long long*>(ws + lay.chunk_sum);
+    a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
     a.n_tiles = (uint32_t)n_tiles;
+    a.n_chunks = (uint32_t)((n_tiles + kChunk - 1) / kChunk);
 
-    // counter word + status words start at zero
-    {
-        pm_status st = fill_u64(reinterpret_cast<uint64_t*>(ws), 0, 1, s);
-        if (st != PM_OK) return st;
-        st = fill_u64(reinterpret_cast<uint64_t*>(a.status), 0, n_tiles, s);
-        if (st != PM_OK) return st;
-    }
-    fn<<<(unsigned)n_tiles, TPB, 0, s>>>(a, plan);
+    fn.count<<<persistent_grid(fn.count, n_tiles), TPB, 0, s>>>(a, plan);
+    HIP_TRY(hipGetLastError());
+    chunk_sum_kernel<<<a.n_chunks, TPB, 0, s>>>(a);
+    HIP_TRY(hipGetLastError());
+    fn.place<<<(unsigned)((n_tiles + 63) / 64), TPB, 0, s>>>(a, plan);
     HIP_TRY(hipGetLastError());
     return PM_OK;
 }

@@ -249,6 +249,25 @@ def test_errors(pm):
         pm.Pattern("")
 
 
+def test_workspace_reuse_across_texts(pm):
+    """One workspace, consecutive scans of different lengths and ranges: the
+    launch counter it carries keeps every call's output exact."""
+    rnd = random.Random(21)
+    big = random_text(rnd, 900000)
+    pat = rand_pattern(rnd, 30, 0.3)
+    plant_copies(rnd, big, pat, 300, 6)
+    tb = pm.encode_text(big)
+    ts = pm.encode_text(big[:50000])
+    P = pm.Pattern(pat)
+    ws = pm.Workspace(tb.data.device, tb.n, 1 << 12)
+    for it in range(12):
+        t, raw = (tb, big) if it % 3 else (ts, big[:50000])
+        b = rnd.randint(0, raw.size // 2) if it % 4 == 3 else 0
+        got = pm.scan(t, P, 6, win_begin=b, ws=ws)
+        got = (got[0].cpu().numpy(), got[1].cpu().numpy())
+        assert_same(got, oracle_hits(raw, pat, 6, win_begin=b), f"reuse {it}")
+
+
 def test_deterministic_repeat(pm):
     rnd = random.Random(12)
     text = random_text(rnd, 400000)
