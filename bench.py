@@ -78,18 +78,14 @@ def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0):
     threads = max(1, min(16, os.cpu_count() or 1))
     sets = oracle.parse(pattern)
     nw = text.size - m + 1
-    probe = min(nw, 5_000_000)
-    while True:  # calibrate on a probe of at least half a second
+    sample = min(nw, 5_000_000)
+    while True:  # grow the sample until one run takes about target_s
         t0 = time.perf_counter()
-        oracle.scan(text, sets, k, threads=threads, win_end=probe, capacity=1 << 16)
+        _, _, hits = oracle.scan(text, sets, k, threads=threads, win_end=sample, capacity=1 << 16)
         dt = time.perf_counter() - t0
-        if dt >= 0.5 or probe >= nw:
+        if dt >= 0.6 * target_s or sample >= nw:
             break
-        probe = min(nw, probe * 4)
-    sample = int(min(nw, max(probe, probe * target_s / dt)))
-    t0 = time.perf_counter()
-    _, _, hits = oracle.scan(text, sets, k, threads=threads, win_end=sample, capacity=1 << 16)
-    dt = time.perf_counter() - t0
+        sample = int(min(nw, sample * min(8.0, max(1.5, target_s / max(dt, 1e-3)))))
     return {
         "value": round(sample * m / dt / 1e9, 3),
         "unit": "G comparisons/s",
@@ -187,6 +183,20 @@ def run_plain(args):
     return result
 
 
+def copy_calibration(gib: float = 1.0, reps: int = 3):
+    """A plain device-to-device copy of a known size, for scaling the HBM
+    byte counters (FETCH_SIZE / WRITE_SIZE) read in counter runs."""
+    import torch
+
+    nbytes = int(gib * (1 << 30))
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,7 +207,12 @@ def main():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter scaling)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
               "by text range with an m-1 overlap and no exchange, see the design notes", flush=True)
