@@ -128,6 +128,49 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
                   void* ws_dev, uint64_t ws_bytes, void* stream);
 
+/* Expected number of hits of a pattern in a text of n i.i.d. uniform bases:
+ * (n-m+1) times the Poisson-binomial probability that at most k of the
+ * pattern's positions mismatch (per-position mismatch probability = number
+ * of bases outside the class / 4).  For sizing output buffers. */
+pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n, double* out);
+
+/* ------------------------------------------------------------------------ *
+ * Batched scan -- many patterns, each with its own k, in one persistent
+ * launch over one encoded text (the scan of each pattern is the one above).
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t group_size;  /* patterns sharing each text tile (1..16); 0 = 4          */
+    uint32_t sub_ranges;  /* text sub-ranges per pattern group (1..1000); 0 = auto   */
+    uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = 6                 */
+    uint32_t reserved;
+} pm_batch_config;
+
+/* Workspace bytes pm_scan_batch needs (depends on the patterns' lengths and
+ * output capacities and on cfg, which may be NULL for the defaults). */
+uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m,
+                                       const uint64_t* capacity, const pm_batch_config* cfg);
+
+/* Scan windows [win_begin, win_end) of the encoded text for `count` patterns.
+ * Host inputs: codes (all patterns' Table 2 codes, concatenated), m[count],
+ * k[count] (each <= 65535), out_off[count] and capacity[count]: pattern p's
+ * hits go to pos_dev/cnt_dev[out_off[p] .. out_off[p]+capacity[p]), in
+ * ascending position order, with exact counts.  Device outputs per pattern:
+ * n_hits_dev[p] = its total number of hits; status_dev[p] = 0 when its list
+ * is complete, 1 when it is not (more than capacity[p] hits, or more than its
+ * share of staging in one text sub-range): such a pattern must be scanned
+ * again (e.g. with pm_scan and an exact buffer).  ws_dev: at least
+ * pm_scan_batch_workspace_bytes(...) bytes, no initialisation needed, used by
+ * one call at a time.  One host-to-device copy of the batch description is
+ * enqueued on `stream` (the host buffer is released before the call returns),
+ * then the kernels. */
+pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const uint8_t* codes,
+                        const uint32_t* m, const uint32_t* k, const uint64_t* out_off,
+                        const uint64_t* capacity, uint64_t win_begin, uint64_t win_end,
+                        int64_t* pos_dev, uint16_t* cnt_dev, uint64_t* n_hits_dev,
+                        uint32_t* status_dev, void* ws_dev, uint64_t ws_bytes,
+                        const pm_batch_config* cfg, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

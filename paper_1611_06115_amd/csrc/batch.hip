@@ -1,0 +1,519 @@
+// batch.hip -- many patterns in one persistent launch (libpmscan).
+//
+// Work item = (group of up to kMaxGroup patterns, text sub-range).  One wave
+// takes an item from a queue, walks the tiles of its sub-range in text order,
+// loads each tile's text and computes its planes once, and runs every pattern
+// of the group on it (each with its own filter plan, counters and exact
+// verification).  A pattern's hits of one sub-range are appended in order to
+// its staging area for that sub-range; a gather kernel then concatenates the
+// sub-ranges of each pattern, in text order, into the caller's output.
+//
+// Patterns in a group share one code path (same filter kind and counter
+// depth); items are queued in decreasing order of estimated cost so that the
+// expensive ones start first.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/pmscan.h"
+#include "plan.hpp"
+#include "scan_core.hpp"
+
+namespace pm {
+// shared with pmscan.hip
+pm_status set_error(pm_status s, const std::string& what);
+uint64_t encoded_text_groups(uint64_t n);
+}  // namespace pm
+
+using namespace pm;
+
+namespace {
+
+constexpr int TPB = kThreads;
+constexpr int kMaxGroup = 16;
+constexpr uint32_t kSkip = 0xFFu;  // variant of a pattern that cannot have hits
+
+struct BatchPattern {
+    ScanPlan plan;        // filter window at the pattern start
+    uint64_t image_off;   // pattern image, in 16-byte units of the image pool
+    uint64_t stage_off;   // staging area, in hits
+    uint64_t nw;          // windows: n - m + 1 (0 when m > n)
+    uint32_t cap_sub;     // staged hits per sub-range
+    uint32_t variant;     // exhaustive << 3 | levels, or kSkip
+    uint32_t index;       // the caller's index of the pattern
+    uint32_t pad_[3];
+};
+static_assert(sizeof(BatchPattern) % 16 == 0, "BatchPattern must keep 16-byte alignment");
+
+struct BatchItem {
+    uint32_t first, count, sub, pad_;  // patterns [first, first+count) of the group, sub-range
+};
+
+struct GatherPattern {
+    uint64_t stage_off, out_off, capacity;
+    uint32_t cap_sub, pad_;
+};
+
+struct BatchArgs {
+    const uint4* text4;
+    uint32_t n4_last;               // last 16-byte group of the text buffer
+    uint32_t n_items;
+    const uint4* images;
+    const BatchPattern* pats;
+    const BatchItem* items;
+    unsigned long long* staged;     // (window << 16) | count
+    uint32_t* counts;               // hits per (caller pattern, sub-range)
+    uint32_t* queue;                // next item
+    uint32_t n_sub;
+    uint32_t pad_;
+    uint64_t win_begin, win_end;    // windows the call reports
+    uint64_t wb0;                   // first block of sub-range 0 (even)
+    uint64_t span_blocks;           // blocks per sub-range (a multiple of the tile)
+};
+
+__device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += v;
+    }
+    total = __shfl(incl, 63, 64);
+    return incl - x;
+}
+
+// One pattern on one tile: filter, verification, and in-order append of the
+// hits to the pattern's staging area for this sub-range.
+template <int R, int L, bool EXH>
+__device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, const BatchPattern& bp, uint32_t sub,
+                                              uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
+                                              uint32_t count_before) {
+    TileSrc src;
+    src.text4 = a.text4;
+    src.image = a.images + bp.image_off;
+    src.win_begin = wlo;
+    src.win_end = whi < bp.nw ? whi : bp.nw;
+    if (src.win_begin >= src.win_end) return 0;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t B = T0 + (uint64_t)lane * R;
+    const bool interior = 32 * T0 >= src.win_begin && 32 * (T0 + 64ull * R) <= src.win_end;
+    Counters<R, L> C;
+    uint32_t hit[R], nh;
+    tile_filter<R, L, EXH>(src, bp.plan, B, interior, s, C, hit, nh);
+    if (__ballot(nh != 0) == 0) return 0;
+    uint32_t total;
+    uint32_t idx = count_before + wave_exclusive(nh, total);
+    unsigned long long* out = a.staged + bp.stage_off + (uint64_t)sub * bp.cap_sub;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        uint32_t h = hit[i];
+        while (h) {
+            const uint32_t b = __builtin_ctz(h);
+            h &= h - 1u;
+            if (idx < bp.cap_sub) {
+                const uint64_t pos = 32 * (B + i) + b;
+                out[idx] = (pos << 16) | hit_count<R, L, EXH>(src, bp.plan, C, i, b, pos);
+            }
+            ++idx;
+        }
+    }
+    return total;
+}
+
+// Counter depth L of a pattern's filter decides its code path.  Two kernels:
+// WIDE = false takes L <= 4 (k - #'-' <= 15), WIDE = true takes L = 5 or 6,
+// so that the common kernel is not sized for the deepest counters.
+template <int R, bool WIDE>
+__device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, const BatchPattern& bp, uint32_t sub,
+                                                uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
+                                                uint32_t before) {
+    switch (bp.variant) {
+#define PM_V(E, L) \
+    case (E) * 8 + (L): return pattern_tile<R, L, (E) != 0>(a, bp, sub, T0, wlo, whi, s, before);
+        PM_V(0, 0) PM_V(0, 1) PM_V(0, 2) PM_V(0, 3) PM_V(0, 4)
+        PM_V(1, 0) PM_V(1, 1) PM_V(1, 2) PM_V(1, 3) PM_V(1, 4)
+#undef PM_V
+        default: break;
+    }
+    if constexpr (WIDE) {
+        switch (bp.variant) {
+            case 5: return pattern_tile<R, 5, false>(a, bp, sub, T0, wlo, whi, s, before);
+            case 6: return pattern_tile<R, 6, false>(a, bp, sub, T0, wlo, whi, s, before);
+            case 13: return pattern_tile<R, 5, true>(a, bp, sub, T0, wlo, whi, s, before);
+            case 14: return pattern_tile<R, 6, true>(a, bp, sub, T0, wlo, whi, s, before);
+            default: break;
+        }
+    }
+    return 0;
+}
+
+template <int R, bool WIDE>
+__global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
+    __shared__ uint32_t s_count[TPB / 64][kMaxGroup];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    while (true) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(a.queue, 1u);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
+        if (item >= a.n_items) break;
+        const BatchItem it = a.items[item];
+        const uint64_t blo = a.wb0 + (uint64_t)it.sub * a.span_blocks;
+        const uint64_t bhi = blo + a.span_blocks;
+        const uint64_t wlo = 32 * blo > a.win_begin ? 32 * blo : a.win_begin;
+        const uint64_t whi = 32 * bhi < a.win_end ? 32 * bhi : a.win_end;
+        if (lane < it.count) s_count[wave][lane] = 0;
+        if (wlo < whi) {
+            const uint64_t tile = 64ull * R;
+            for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
+                // text of the tile from its first block (filter windows start at 0)
+                uint4 txt[(R + 2) / 2];
+                const uint32_t g0 = (uint32_t)(T0 >> 1) + lane * (R / 2);
+#pragma unroll
+                for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
+                Lane<R> s;
+                make_lane<R>(txt, 15u, s);
+                for (uint32_t g = 0; g < it.count; ++g) {
+                    const BatchPattern& bp = a.pats[it.first + g];
+                    const uint32_t before = s_count[wave][g];
+                    const uint32_t got = run_pattern<R, WIDE>(a, bp, it.sub, T0, wlo, whi, s, before);
+                    if (lane == 0) s_count[wave][g] = before + got;
+                }
+            }
+        }
+        if (lane < it.count) a.counts[(uint64_t)a.pats[it.first + lane].index * a.n_sub + it.sub] = s_count[wave][lane];
+    }
+}
+
+// One workgroup per pattern: concatenate its sub-ranges in text order.
+__global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* gp, const uint32_t* counts,
+                                                           uint32_t n_sub, const unsigned long long* staged,
+                                                           int64_t* pos, uint16_t* cnt,
+                                                           unsigned long long* n_hits, uint32_t* status) {
+    __shared__ unsigned long long s_off[1024];
+    __shared__ uint32_t s_flag;
+    const uint32_t p = blockIdx.x;
+    const GatherPattern g = gp[p];
+    if (threadIdx.x == 0) {
+        unsigned long long run = 0;
+        uint32_t over = 0;
+        for (uint32_t s = 0; s < n_sub; ++s) {
+            const uint32_t c = counts[(uint64_t)p * n_sub + s];
+            s_off[s] = run;
+            run += c;
+            if (c > g.cap_sub) over = 1;
+        }
+        s_off[n_sub] = run;
+        if (run > g.capacity) over = 1;
+        n_hits[p] = run;
+        status[p] = over;
+        s_flag = over;
+    }
+    __syncthreads();
+    if (s_flag) return;
+    for (uint32_t s = 0; s < n_sub; ++s) {
+        const uint64_t first = s_off[s];
+        const uint32_t c = (uint32_t)(s_off[s + 1] - first);
+        const unsigned long long* src = staged + g.stage_off + (uint64_t)s * g.cap_sub;
+        for (uint32_t i = threadIdx.x; i < c; i += TPB) {
+            const unsigned long long v = src[i];
+            pos[g.out_off + first + i] = (int64_t)(v >> 16);
+            cnt[g.out_off + first + i] = (uint16_t)(v & 0xFFFFu);
+        }
+    }
+}
+
+__global__ void fill_zero_kernel(uint32_t* p, uint64_t words) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < words; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+struct BatchShape {
+    uint32_t G, S, R;
+    uint64_t span_blocks, wb0;
+};
+
+struct BatchLayout {
+    uint64_t pats, items, images, gather, queue, counts, staged, bytes;
+    std::vector<uint64_t> image_off, stage_off;
+    std::vector<uint32_t> cap_sub;
+    uint64_t n_items_max;
+};
+
+BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, uint64_t win_begin,
+                       uint64_t win_end) {
+    BatchShape sh;
+    sh.G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 4;
+    sh.R = cfg && cfg->lane_words == 4 ? 4 : 6;
+    const uint64_t groups = (count + sh.G - 1) / sh.G;
+    uint32_t S = cfg && cfg->sub_ranges ? cfg->sub_ranges : 0;
+    if (S == 0) {
+        // about 8 items per wave that fits on the device (~16 per CU)
+        const uint64_t want = 8ull * 256 * 16;
+        S = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (want + groups - 1) / std::max<uint64_t>(groups, 1)));
+    }
+    S = std::min<uint32_t>(S, 1000);
+    sh.S = S;
+    if (win_end > n) win_end = n;
+    if (win_begin > win_end) win_begin = win_end;
+    sh.wb0 = (win_begin / 32) & ~1ull;
+    const uint64_t tile = 64ull * sh.R;
+    const uint64_t blocks = (win_end + 31) / 32 - sh.wb0 + 1;
+    const uint64_t per = (blocks + S - 1) / S;
+    sh.span_blocks = std::max<uint64_t>(tile, (per + tile - 1) / tile * tile);
+    return sh;
+}
+
+BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capacity, const BatchShape& sh) {
+    BatchLayout L;
+    L.image_off.resize(count);
+    L.stage_off.resize(count);
+    L.cap_sub.resize(count);
+    L.n_items_max = (uint64_t)((count + sh.G - 1) / sh.G) * sh.S + (uint64_t)count * sh.S;
+    uint64_t img = 0, stg = 0;
+    for (uint32_t p = 0; p < count; ++p) {
+        L.image_off[p] = img;
+        img += (m[p] + 31) / 32;
+        const uint64_t c = capacity[p];
+        const uint64_t cs = std::min<uint64_t>(c, (2 * c + sh.S - 1) / sh.S + 16);
+        L.cap_sub[p] = (uint32_t)std::min<uint64_t>(cs, 0xFFFFFFF0ull);
+        L.stage_off[p] = stg;
+        stg += (uint64_t)sh.S * L.cap_sub[p];
+    }
+    uint64_t off = 0;
+    L.pats = off;
+    off = align256(off + sizeof(BatchPattern) * (uint64_t)count);
+    L.items = off;
+    off = align256(off + sizeof(BatchItem) * L.n_items_max);
+    L.gather = off;
+    off = align256(off + sizeof(GatherPattern) * (uint64_t)count);
+    L.images = off;
+    off = align256(off + 16 * img);
+    L.queue = off;
+    off = align256(off + 8);
+    L.counts = off;
+    off = align256(off + 4ull * count * sh.S);
+    L.staged = off;
+    off = align256(off + 8 * stg);
+    L.bytes = off;
+    return L;
+}
+
+pm_status check_batch_args(uint32_t count, const uint32_t* m, const uint32_t* k, const uint64_t* capacity) {
+    if (count == 0) return PM_OK;
+    if (!m || !k || !capacity) return set_error(PM_ERR_ARG, "null pointer");
+    for (uint32_t p = 0; p < count; ++p) {
+        if (m[p] == 0) return set_error(PM_ERR_ARG, "pattern " + std::to_string(p) + " is empty");
+        if (k[p] > 65535) return set_error(PM_ERR_ARG, "k above 65535 for pattern " + std::to_string(p));
+    }
+    return PM_OK;
+}
+
+using BatchFn = void (*)(BatchArgs);
+
+unsigned batch_grid(BatchFn fn, uint64_t items) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), TPB, 0) !=
+            hipSuccess ||
+        cus <= 0 || per_cu <= 0) {
+        cus = 256;
+        per_cu = 2;
+    }
+    const uint64_t waves_needed = items;
+    const uint64_t blocks = std::min<uint64_t>((uint64_t)cus * per_cu, (waves_needed + 3) / 4);
+    return (unsigned)std::max<uint64_t>(blocks, 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n, double* out) {
+    if (!codes || !out) return set_error(PM_ERR_ARG, "null pointer");
+    for (uint32_t j = 0; j < m; ++j)
+        if (codes[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15");
+    *out = expected_hits(codes, m, k, n);
+    return PM_OK;
+}
+
+uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
+                                       const pm_batch_config* cfg) {
+    if (count == 0 || !m || !capacity) return 256;
+    const BatchShape sh = batch_shape(n, count, cfg, 0, n);
+    return batch_layout(count, m, capacity, sh).bytes;
+}
+
+pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const uint8_t* codes,
+                        const uint32_t* m, const uint32_t* k, const uint64_t* out_off, const uint64_t* capacity,
+                        uint64_t win_begin, uint64_t win_end, int64_t* pos_dev, uint16_t* cnt_dev,
+                        uint64_t* n_hits_dev, uint32_t* status_dev, void* ws_dev, uint64_t ws_bytes,
+                        const pm_batch_config* cfg, void* stream) {
+    if (count == 0) return PM_OK;
+    if (!text_dev || !codes || !out_off || !n_hits_dev || !status_dev || !ws_dev)
+        return set_error(PM_ERR_ARG, "null pointer");
+    pm_status st = check_batch_args(count, m, k, capacity);
+    if (st != PM_OK) return st;
+    if (reinterpret_cast<uintptr_t>(text_dev) % 16 != 0) return set_error(PM_ERR_ARG, "text_dev must be 16-byte aligned");
+    if (encoded_text_groups(n) >= (1ull << 32)) return set_error(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
+    for (uint32_t p = 0; p < count; ++p)
+        if (capacity[p] > 0 && (!pos_dev || !cnt_dev)) return set_error(PM_ERR_ARG, "null output with capacity > 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (win_end > n) win_end = n;
+    if (win_begin > win_end) win_begin = win_end;
+    // The workspace is laid out for the whole text (full.S sub-ranges per
+    // pattern).  A call uses only as many sub-ranges as its window range
+    // fills with whole tiles, and gives each the staging of the unused ones.
+    const BatchShape full = batch_shape(n, count, cfg, 0, n);
+    BatchLayout L = batch_layout(count, m, capacity, full);
+    if (ws_bytes < L.bytes)
+        return set_error(PM_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.bytes) + " bytes");
+    BatchShape sh = full;
+    {
+        const uint64_t tile = 64ull * sh.R;
+        sh.wb0 = (win_begin / 32) & ~1ull;
+        const uint64_t blocks = (win_end + 31) / 32 - sh.wb0 + 1;
+        sh.S = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(full.S, (blocks + tile - 1) / tile));
+        const uint64_t per = (blocks + sh.S - 1) / sh.S;
+        sh.span_blocks = (per + tile - 1) / tile * tile;
+        for (uint32_t p = 0; p < count; ++p)
+            L.cap_sub[p] = (uint32_t)std::min<uint64_t>((uint64_t)full.S * L.cap_sub[p] / sh.S, 0xFFFFFFF0ull);
+    }
+
+    // plans, images, groups and queue order on the host
+    std::vector<uint64_t> code_off(count + 1, 0);
+    for (uint32_t p = 0; p < count; ++p) code_off[p + 1] = code_off[p] + m[p];
+    std::vector<BatchPattern> pats(count);
+    std::vector<GatherPattern> gat(count);
+    // the image pool occupies [L.images, L.queue) of the descriptor region
+    std::vector<uint32_t> img_words((L.queue - L.images) / 4, 0u);
+    std::vector<double> cost(count, 0.0);
+    for (uint32_t p = 0; p < count; ++p) {
+        const uint8_t* c = codes + code_off[p];
+        for (uint32_t j = 0; j < m[p]; ++j)
+            if (c[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15 in pattern " + std::to_string(p));
+        BatchPattern& bp = pats[p];
+        std::memset(&bp, 0, sizeof(bp));
+        bp.plan = build_plan(c, m[p], k[p], 4e-5, /*window_at_zero=*/true);
+        bp.image_off = L.image_off[p];
+        bp.stage_off = L.stage_off[p];
+        bp.cap_sub = L.cap_sub[p];
+        bp.nw = m[p] <= n ? n - m[p] + 1 : 0;
+        bp.index = p;
+        const bool skip = bp.plan.keff < 0 || bp.nw == 0 || bp.nw <= win_begin;
+        bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels;
+        build_image(c, m[p], img_words.data() + 4 * L.image_off[p]);
+        // cost per tile: filter slots, plus a full count per window without a filter
+        cost[p] = skip ? 0.0
+                       : (bp.plan.n_slots > 0 || bp.plan.exhaustive ? 8.0 + bp.plan.n_slots
+                                                                    : 8.0 + 32.0 * 10.0 * bp.plan.nchunks);
+        gat[p].stage_off = L.stage_off[p];
+        gat[p].out_off = out_off[p];
+        gat[p].capacity = capacity[p];
+        gat[p].cap_sub = L.cap_sub[p];
+    }
+    // groups: same variant, similar cost; items: (group, sub-range), costly first
+    std::vector<uint32_t> order(count);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        if (pats[x].variant != pats[y].variant) return pats[x].variant < pats[y].variant;
+        return cost[x] > cost[y];
+    });
+    std::vector<BatchPattern> sorted(count);
+    for (uint32_t i = 0; i < count; ++i) sorted[i] = pats[order[i]];
+    struct Group {
+        uint32_t first, count;
+        double cost;
+    };
+    std::vector<Group> groups;
+    for (uint32_t i = 0; i < count;) {
+        uint32_t j = i;
+        double c = 0;
+        while (j < count && j - i < sh.G && sorted[j].variant == sorted[i].variant) c += cost[order[j++]];
+        groups.push_back({i, j - i, c});
+        i = j;
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.cost > y.cost; });
+    // common items first, then the items of patterns with 5 or 6 counter levels
+    std::vector<BatchItem> items;
+    items.reserve(groups.size() * sh.S);
+    auto is_wide = [&](const Group& g) { return (sorted[g.first].variant & 7u) >= 5u; };
+    for (int pass = 0; pass < 2; ++pass)
+        for (const Group& g : groups) {
+            if (g.cost == 0.0 || is_wide(g) != (pass == 1)) continue;
+            for (uint32_t sub = 0; sub < sh.S; ++sub) items.push_back({g.first, g.count, sub, 0});
+        }
+    size_t n_common = 0;
+    while (n_common < items.size() && (sorted[items[n_common].first].variant & 7u) < 5u) ++n_common;
+    if (items.size() > L.n_items_max) return set_error(PM_ERR_ARG, "internal: too many work items");
+
+    uint8_t* ws = reinterpret_cast<uint8_t*>(ws_dev);
+    hipError_t e;
+    // one copy of the descriptor region (patterns .. images)
+    std::vector<uint8_t> desc(L.queue, 0);
+    std::memcpy(desc.data() + L.pats, sorted.data(), sizeof(BatchPattern) * count);
+    if (!items.empty()) std::memcpy(desc.data() + L.items, items.data(), sizeof(BatchItem) * items.size());
+    std::memcpy(desc.data() + L.gather, gat.data(), sizeof(GatherPattern) * count);
+    std::memcpy(desc.data() + L.images, img_words.data(), 4 * img_words.size());
+    if ((e = hipMemcpyAsync(ws, desc.data(), desc.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return set_error(PM_ERR_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+    // queue and per-(pattern, sub-range) counts start at zero (patterns that
+    // get no work item keep zero counts)
+    fill_zero_kernel<<<1024, TPB, 0, s>>>(reinterpret_cast<uint32_t*>(ws + L.queue),
+                                          (L.staged - L.queue) / 4);
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
+
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.text4 = reinterpret_cast<const uint4*>(text_dev);
+    a.n4_last = (uint32_t)(encoded_text_groups(n) - 1);
+    a.n_items = (uint32_t)items.size();
+    a.images = reinterpret_cast<const uint4*>(ws + L.images);
+    a.pats = reinterpret_cast<const BatchPattern*>(ws + L.pats);
+    a.items = reinterpret_cast<const BatchItem*>(ws + L.items);
+    a.staged = reinterpret_cast<unsigned long long*>(ws + L.staged);
+    a.counts = reinterpret_cast<uint32_t*>(ws + L.counts);
+    a.queue = reinterpret_cast<uint32_t*>(ws + L.queue);
+    a.n_sub = sh.S;
+    a.win_begin = win_begin;
+    a.win_end = win_end;
+    a.wb0 = sh.wb0;
+    a.span_blocks = sh.span_blocks;
+    // two launches at most: the common kernel, and the deep-counter one on
+    // its own queue word (queue + 1) over the remaining items
+    if (n_common > 0) {
+        BatchFn fn = sh.R == 4 ? batch_kernel<4, false> : batch_kernel<6, false>;
+        a.n_items = (uint32_t)n_common;
+        fn<<<batch_grid(fn, n_common), TPB, 0, s>>>(a);
+        if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
+    }
+    if (items.size() > n_common) {
+        BatchFn fn = sh.R == 4 ? batch_kernel<4, true> : batch_kernel<6, true>;
+        BatchArgs w = a;
+        w.items = a.items + n_common;
+        w.n_items = (uint32_t)(items.size() - n_common);
+        w.queue = a.queue + 1;
+        fn<<<batch_grid(fn, w.n_items), TPB, 0, s>>>(w);
+        if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
+    }
+    batch_gather_kernel<<<count, TPB, 0, s>>>(reinterpret_cast<const GatherPattern*>(ws + L.gather), a.counts, sh.S,
+                                              a.staged, pos_dev, cnt_dev,
+                                              reinterpret_cast<unsigned long long*>(n_hits_dev), status_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
+    return PM_OK;
+}
+
+}  // extern "C"

@@ -117,7 +117,7 @@ void build_image(const uint8_t* codes, uint32_t m, uint32_t* out) {
     }
 }
 
-ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival) {
+ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival, bool window_at_zero) {
     ScanPlan p;
     std::memset(&p, 0, sizeof(p));
     p.m = m;
@@ -149,7 +149,7 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
     for (uint32_t j = 0; j < m; ++j)
         if (countable(j)) ++n_countable;
     uint32_t best_fw = 0, best_single = 0;
-    for (uint32_t fw = 0; 32 * fw < m; fw += 2) {
+    for (uint32_t fw = 0; 32 * fw < m && (fw == 0 || !window_at_zero); fw += 2) {
         uint32_t c = 0;
         for (uint32_t j = 32 * fw; j < std::min(m, 32 * fw + 64); ++j)
             if (is_single(j)) ++c;
@@ -165,7 +165,7 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
             first = std::min(first, j);
             last = j;
         }
-    const uint32_t ex_fw = n_countable ? (first / 32) & ~1u : 0;
+    const uint32_t ex_fw = n_countable && !window_at_zero ? (first / 32) & ~1u : 0;
     const bool can_exhaust = n_countable == 0 || last < 32 * ex_fw + 64;
 
     // survival of a random window (uniform bases) for J singleton slots
@@ -222,6 +222,23 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
         }
     }
     return p;
+}
+
+double expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n) {
+    if (m == 0 || m > n) return 0.0;
+    std::vector<double> d(k + 2, 0.0);  // d[c] = P(count = c), c > k folded into d[k+1]
+    d[0] = 1.0;
+    for (uint32_t j = 0; j < m; ++j) {
+        const double q = __builtin_popcount(mismatch_mask(codes[j])) / 4.0;
+        if (q == 0.0) continue;
+        for (int c = static_cast<int>(k) + 1; c >= 0; --c) {
+            const double stay = d[c] * (c == static_cast<int>(k) + 1 ? 1.0 : 1.0 - q);
+            d[c] = stay + (c > 0 ? d[c - 1] * q : 0.0);
+        }
+    }
+    double p = 0;
+    for (uint32_t c = 0; c <= k; ++c) p += d[c];
+    return p * static_cast<double>(n - m + 1);
 }
 
 }  // namespace pm

@@ -60,6 +60,14 @@ inline uint64_t image_words(uint32_t m) { return 4ull * ((m + 31) / 32); }
 // Filter plan for (pattern, k).  `survival` is the target probability that a
 // random window survives the filter (survivors are counted exactly one by
 // one, so a few per 16K windows cost little).
-ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival = 4e-5);
+// With window_at_zero the filter window is the pattern's first 64 positions
+// (patterns that share one text tile then share its planes).
+ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival = 4e-5,
+                    bool window_at_zero = false);
+
+// Expected number of windows with at most k mismatches in a text of n
+// i.i.d. uniform bases (Poisson-binomial tail of the per-position mismatch
+// probabilities |bases outside the class| / 4).
+double expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n);
 
 }  // namespace pm

@@ -33,8 +33,10 @@
 
 #include "../../include/pmscan.h"
 #include "plan.hpp"
+#include "scan_core.hpp"
 
 using pm::ScanPlan;
+using namespace pm;
 
 namespace {
 
@@ -152,11 +154,11 @@ constexpr int kCap = 32;      // hits a tile stages for the placement kernel
 constexpr int kChunk = 1024;  // tiles per chunk of the hit-count prefix
 
 struct ScanArgs {
-    const uint4* text4;        // encoded text as 16-byte groups (two blocks each)
+    TileSrc src;               // text (16-byte groups), pattern image, window range
+    const uint4* text4;        // = src.text4
     uint64_t n4;               // 16-byte groups in the buffer
     uint64_t wb0;              // first block of tile 0 (even)
     uint64_t win_begin, win_end;
-    const uint4* image;        // pattern image, one uint4 (A,C,G,T planes) per chunk
     int64_t* pos;
     uint16_t* cnt;
     uint64_t capacity;
@@ -167,155 +169,6 @@ struct ScanArgs {
     uint32_t n_tiles, n_chunks;
 };
 
-// Mismatch word of 32 windows for one pattern position, from the text's high
-// (H) and low (L) code-bit planes at that position: the OR of the minterms of
-// the text codes in the position's Table 3 row MM.
-template <unsigned MM>
-__device__ __forceinline__ uint32_t mismatch_fn(uint32_t H, uint32_t L) {
-    uint32_t x = 0;
-    if (MM & 1u) x |= ~H & ~L;  // A = 00
-    if (MM & 2u) x |= ~H & L;   // C = 01
-    if (MM & 4u) x |= H & ~L;   // G = 10
-    if (MM & 8u) x |= H & L;    // T = 11
-    return x;
-}
-
-__device__ __forceinline__ uint32_t align(uint32_t hi, uint32_t lo, uint32_t r) {
-    return __builtin_amdgcn_alignbit(hi, lo, r);
-}
-
-template <int R>
-struct Lane {
-    uint32_t h[R + 2], l[R + 2];  // raw planes of blocks B+fw .. B+fw+R+1
-    uint32_t P[4][R + 2];          // P[c]: mismatch plane of singleton base c
-};
-
-// Singleton-filter slot (c | q << 2 | r << 3): mismatch words of the 32*R
-// windows of the lane for the position 32*q + r of the filter window whose
-// class is the single base c.  The dispatch over (c, q) is uniform.
-template <int C, int Q, int R>
-__device__ __forceinline__ void single_words(const Lane<R>& s, uint32_t r, uint32_t (&X)[R]) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) X[i] = align(s.P[C][i + Q + 1], s.P[C][i + Q], r);
-}
-
-template <int R>
-__device__ __forceinline__ void single_slot(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
-    const uint32_t r = slot >> 3;
-    switch (slot & 7u) {
-        case 0: single_words<0, 0, R>(s, r, X); break;
-        case 1: single_words<1, 0, R>(s, r, X); break;
-        case 2: single_words<2, 0, R>(s, r, X); break;
-        case 3: single_words<3, 0, R>(s, r, X); break;
-        case 4: single_words<0, 1, R>(s, r, X); break;
-        case 5: single_words<1, 1, R>(s, r, X); break;
-        case 6: single_words<2, 1, R>(s, r, X); break;
-        default: single_words<3, 1, R>(s, r, X); break;
-    }
-}
-
-// Exhaustive-filter slot (mm | q << 4 | r << 5): any class, its Table 3 row
-// mm applied to the shifted planes without branching on it.
-template <int Q, int R>
-__device__ __forceinline__ void general_words(const Lane<R>& s, uint32_t r, uint32_t mA, uint32_t mC,
-                                              uint32_t mG, uint32_t mT, uint32_t (&X)[R]) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        const uint32_t H = align(s.h[i + Q + 1], s.h[i + Q], r);
-        const uint32_t L = align(s.l[i + Q + 1], s.l[i + Q], r);
-        X[i] = (H & ((L & mT) | (~L & mG))) | (~H & ((L & mC) | (~L & mA)));
-    }
-}
-
-template <int R>
-__device__ __forceinline__ void general_slot(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
-    const uint32_t r = slot >> 5;
-    const uint32_t mA = 0u - (slot & 1u), mC = 0u - (slot >> 1 & 1u);
-    const uint32_t mG = 0u - (slot >> 2 & 1u), mT = 0u - (slot >> 3 & 1u);
-    if (slot & 16u) general_words<1, R>(s, r, mA, mC, mG, mT, X);
-    else general_words<0, R>(s, r, mA, mC, mG, mT, X);
-}
-
-// Full-adder halves as single three-input LUT operations (v_bitop3_b32);
-// both functions are symmetric in their inputs.
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-__device__ __forceinline__ uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xE8);
-}
-__device__ __forceinline__ uint32_t or3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0xFE);
-}
-
-// Bit-sliced counters: S[l][i] is bit l of the counts of the 32 windows of
-// lane word i, started at `init` = 2^L - (keff+1), so a window whose count
-// reaches keff+1 carries out of the top level; carries out of level L set
-// its `dead` bit.
-template <int R, int L>
-struct Counters {
-    uint32_t S[L > 0 ? L : 1][R];
-    uint32_t dead[R];
-};
-
-// Add two carry words (weight 2^LV) to the counters.  Returns the carry into
-// level LV+1 in `out`.
-template <int LV, int R, int L>
-__device__ __forceinline__ void add2(Counters<R, L>& c, const uint32_t (&a)[R], const uint32_t (&b)[R],
-                                     uint32_t (&out)[R]) {
-    if constexpr (LV == L) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) c.dead[i] = or3(c.dead[i], a[i], b[i]);
-    } else if constexpr (LV < L) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const uint32_t s = c.S[LV][i];
-            c.S[LV][i] = xor3(s, a[i], b[i]);
-            out[i] = maj3(s, a[i], b[i]);
-        }
-    }
-}
-
-template <int LV, int R, int L>
-__device__ __forceinline__ void add1(Counters<R, L>& c, uint32_t (&a)[R]) {
-    if constexpr (LV == L) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) c.dead[i] |= a[i];
-    } else if constexpr (LV < L) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            const uint32_t s = c.S[LV][i];
-            c.S[LV][i] = s ^ a[i];
-            a[i] = s & a[i];
-        }
-        add1<LV + 1, R, L>(c, a);
-    }
-}
-
-// Exact count of one window, all m positions (pattern image), stopping once
-// the count exceeds `limit`.
-__device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* __restrict__ image,
-                                 uint32_t nchunks, uint64_t s, uint32_t limit) {
-    const uint2* text = reinterpret_cast<const uint2*>(text4);
-    const uint64_t q = s >> 5;
-    const uint32_t r = (uint32_t)s & 31u;
-    uint2 w0 = text[q];
-    uint32_t cnt = 0;
-    for (uint32_t c = 0; c < nchunks; ++c) {
-        const uint2 w1 = text[q + c + 1];
-        const uint32_t H = align(w1.x, w0.x, r), Lo = align(w1.y, w0.y, r);
-        const uint4 mp = image[c];
-        const uint32_t mis = (~H & ~Lo & mp.x) | (~H & Lo & mp.y) | (H & ~Lo & mp.z) | (H & Lo & mp.w);
-        cnt += __builtin_popcount(mis);
-        if (cnt > limit) break;
-        w0 = w1;
-    }
-    return cnt;
-}
-
-// Filter + verification of one tile: hit[i] gets the windows of lane word i
-// (32*(B+i) + bit) with at most k mismatches; C keeps the filter counters
-// (exact counts when the plan is exhaustive).
 // The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
 // (B and fw are even).  Lanes past the end of the text read the last group.
 template <int R>
@@ -344,136 +197,6 @@ __device__ __forceinline__ void load_tile_text(const ScanArgs& a, const ScanPlan
     for (int u = 0; u < (R + 2) / 2; ++u) t[u] = a.text4[min(g0 + (uint32_t)u, last)];
 }
 
-template <int R, int L, bool EXH>
-__device__ __forceinline__ void tile_hits(const ScanArgs& a, const ScanPlan& p, uint64_t B, bool interior,
-                                          const uint4 (&t)[(R + 2) / 2], Counters<R, L>& C,
-                                          uint32_t (&hit)[R], uint32_t& nh) {
-    // ---- valid windows of each lane word ------------------------------------
-    // (windows outside [win_begin, win_end) start dead; `interior` says the
-    // whole tile lies inside, which holds for all tiles but the edge ones)
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        uint32_t valid = ~0u;
-        if (!interior) {
-            const uint64_t w0 = 32 * (B + i);
-            valid = 0;
-            if (w0 < a.win_end && w0 + 32 > a.win_begin) {
-                const uint32_t lo = a.win_begin > w0 ? (uint32_t)(a.win_begin - w0) : 0u;
-                const uint32_t hi = a.win_end < w0 + 32 ? (uint32_t)(a.win_end - w0) : 32u;
-                valid = (hi == 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
-            }
-        }
-        C.dead[i] = ~valid;
-        if constexpr (L > 0) {
-#pragma unroll
-            for (int l = 0; l < L; ++l) C.S[l][i] = (p.init >> l & 1u) ? ~0u : 0u;
-        }
-    }
-
-    // ---- filter ---------------------------------------------------------------
-    if (p.n_slots > 0) {
-        Lane<R> s;
-#pragma unroll
-        for (int u = 0; u < (R + 2) / 2; ++u) {
-            s.h[2 * u] = t[u].x;
-            s.l[2 * u] = t[u].y;
-            s.h[2 * u + 1] = t[u].z;
-            s.l[2 * u + 1] = t[u].w;
-        }
-        if constexpr (!EXH) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (p.singles >> c & 1u) {
-#pragma unroll
-                    for (int w = 0; w < R + 2; ++w) {
-                        // mismatch with base c: the text code differs from c
-                        const uint32_t hx = (c & 2) ? ~s.h[w] : s.h[w];
-                        const uint32_t lx = (c & 1) ? ~s.l[w] : s.l[w];
-                        s.P[c][w] = hx | lx;
-                    }
-                }
-            }
-        }
-
-        const uint4* groups = reinterpret_cast<const uint4*>(p.slot);  // 8 slots per 16 bytes
-        for (uint32_t g = 0; g < p.n_slots; g += 8) {
-            const uint4 gw = groups[g >> 3];
-            const uint32_t gv[4] = {gw.x, gw.y, gw.z, gw.w};
-            uint32_t xa[R], xb[R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
-#pragma unroll
-            for (int half = 0; half < 2; ++half) {
-#pragma unroll
-                for (int pr = 0; pr < 2; ++pr) {
-                    const uint32_t w = gv[2 * half + pr];  // slots u and u+1
-                    if constexpr (EXH) {
-                        general_slot<R>(w & 0xFFFFu, s, xa);
-                        general_slot<R>(w >> 16, s, xb);
-                    } else {
-                        single_slot<R>(w & 0xFFFFu, s, xa);
-                        single_slot<R>(w >> 16, s, xb);
-                    }
-                    if constexpr (L == 0) {
-#pragma unroll
-                        for (int i = 0; i < R; ++i) C.dead[i] = or3(C.dead[i], xa[i], xb[i]);
-                    } else {
-                        add2<0, R, L>(C, xa, xb, pr == 0 ? c0a : c0b);
-                    }
-                }
-                add2<1, R, L>(C, c0a, c0b, half == 0 ? c1a : c1b);
-            }
-            add2<2, R, L>(C, c1a, c1b, c2);
-            if constexpr (L >= 3) add1<3, R, L>(C, c2);
-        }
-    }
-
-    // ---- survivors -> hits -----------------------------------------------------
-    nh = 0;
-    if constexpr (EXH) {
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            hit[i] = ~C.dead[i];
-            nh += __builtin_popcount(hit[i]);
-        }
-    } else {
-        uint32_t any = 0;
-#pragma unroll
-        for (int i = 0; i < R; ++i) any |= ~C.dead[i];
-        if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
-#pragma unroll
-            for (int i = 0; i < R; ++i) hit[i] = 0;
-            return;
-        }
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            uint32_t alive = ~C.dead[i];
-            uint32_t h = 0;
-            while (alive) {
-                const uint32_t b = __builtin_ctz(alive);
-                alive &= alive - 1u;
-                const uint32_t c = count_window(a.text4, a.image, p.nchunks, 32 * (B + i) + b, p.k);
-                if (c <= p.k) h |= 1u << b;
-            }
-            hit[i] = h;
-            nh += __builtin_popcount(h);
-        }
-    }
-}
-
-// Exact count of hit window `b` of lane word i.
-template <int R, int L, bool EXH>
-__device__ __forceinline__ uint32_t hit_count(const ScanArgs& a, const ScanPlan& p, const Counters<R, L>& C,
-                                              int i, uint32_t b, uint64_t pos) {
-    if constexpr (EXH) {
-        uint32_t v = 0;
-        if constexpr (L > 0) {
-#pragma unroll
-            for (int l = 0; l < L; ++l) v |= (C.S[l][i] >> b & 1u) << l;
-        }
-        return v - p.init + p.n_dash;
-    }
-    return count_window(a.text4, a.image, p.nchunks, pos, p.k);
-}
-
 // Write the hits of this lane, in order, starting at output index `idx`.
 template <int R, int L, bool EXH>
 __device__ __forceinline__ void write_hits(const ScanArgs& a, const ScanPlan& p, const Counters<R, L>& C,
@@ -487,7 +210,7 @@ __device__ __forceinline__ void write_hits(const ScanArgs& a, const ScanPlan& p,
             if (idx < a.capacity) {
                 const uint64_t pos = 32 * (B + i) + b;
                 a.pos[idx] = (int64_t)pos;
-                a.cnt[idx] = (uint16_t)hit_count<R, L, EXH>(a, p, C, i, b, pos);
+                a.cnt[idx] = (uint16_t)hit_count<R, L, EXH>(a.src, p, C, i, b, pos);
             }
             ++idx;
         }
@@ -531,7 +254,9 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
         load_tile_text<R>(a, p, T0, txt);
         Counters<R, L> C;
         uint32_t hit[R], nh;
-        tile_hits<R, L, EXH>(a, p, B, tile_interior(a, T0, R), txt, C, hit, nh);
+        Lane<R> s;
+        make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
+        tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
         if (__ballot(nh != 0) == 0) {  // the usual case: no hits in the tile
             if (lane == 0) a.counts[tile] = 0;
             continue;
@@ -549,7 +274,7 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
                 const uint32_t b = __builtin_ctz(h);
                 h &= h - 1u;
                 const uint64_t pos = 32 * (B + i) + b;
-                const uint32_t c = hit_count<R, L, EXH>(a, p, C, i, b, pos);
+                const uint32_t c = hit_count<R, L, EXH>(a.src, p, C, i, b, pos);
                 *out++ = ((pos - base) << 16) | c;
             }
         }
@@ -657,7 +382,9 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
         load_text<R>(a, p, B, txt);
         Counters<R, L> C;
         uint32_t hit[R], nh;
-        tile_hits<R, L, EXH>(a, p, B, tile_interior(a, T0, R), txt, C, hit, nh);
+        Lane<R> s;
+        make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
+        tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
         uint32_t total;
         const uint32_t excl = wave_exclusive(nh, total);
         if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, s_prefix[l] + excl);
@@ -727,6 +454,11 @@ WsLayout ws_layout(uint64_t T) {
 }
 
 }  // namespace
+
+namespace pm {
+pm_status set_error(pm_status s, const std::string& what) { return fail(s, what); }
+uint64_t encoded_text_groups(uint64_t n) { return text_blocks(n) / 2; }
+}  // namespace pm
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -843,11 +575,14 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     const WsLayout lay = ws_layout(max_tiles(n));
     ScanArgs a;
     a.text4 = reinterpret_cast<const uint4*>(text_dev);
+    a.src.text4 = a.text4;
+    a.src.image = reinterpret_cast<const uint4*>(image_dev);
+    a.src.win_begin = win_begin;
+    a.src.win_end = win_end;
     a.n4 = text_blocks(n) / 2;
     a.wb0 = wb0;
     a.win_begin = win_begin;
     a.win_end = win_end;
-    a.image = reinterpret_cast<const uint4*>(image_dev);
     a.pos = pos_dev;
     a.cnt = cnt_dev;
     a.capacity = capacity;

@@ -47,6 +47,10 @@ def lib():
             "pm_pattern_image": ([vp, u32, vp, u64], i32),
             "pm_scan_workspace_bytes": ([u64], u64),
             "pm_scan": ([vp, u64, vp, u32, u32, vp, u64, u64, vp, vp, u64, vp, vp, u64, vp], i32),
+            "pm_expected_hits": ([vp, u32, u32, u64, ctypes.POINTER(ctypes.c_double)], i32),
+            "pm_scan_batch_workspace_bytes": ([u64, u32, vp, vp, vp], u64),
+            "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
+                              i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -222,3 +226,96 @@ def scan(text: Text, pattern: Pattern | str, k: int, win_begin: int = 0, win_end
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
         total = int(ws.n_hits.item())
     return ws.pos[:total].clone(), ws.cnt[:total].clone()
+
+
+# --- batched scan ----------------------------------------------------------------
+
+class BatchConfig(ctypes.Structure):
+    """pm_batch_config: patterns per text tile, sub-ranges, lane words."""
+    _fields_ = [("group_size", ctypes.c_uint32), ("sub_ranges", ctypes.c_uint32),
+                ("lane_words", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def expected_hits(pattern: "Pattern", k: int, n: int) -> float:
+    out = ctypes.c_double(0.0)
+    check(lib().pm_expected_hits(pattern.codes.ctypes.data, pattern.m, int(k), int(n), ctypes.byref(out)))
+    return out.value
+
+
+def default_capacity(pattern: "Pattern", k: int, n: int) -> int:
+    """Output slots for a pattern: twice the expected hits plus a margin."""
+    return int(2 * expected_hits(pattern, k, n)) + 64
+
+
+class Batch:
+    """Host arrays of a batch of patterns (codes, lengths, budgets, capacities)."""
+
+    def __init__(self, patterns, ks, n: int, capacities=None):
+        self.patterns = [p if isinstance(p, Pattern) else Pattern(p) for p in patterns]
+        self.ks = np.ascontiguousarray(ks, dtype=np.uint32)
+        if self.ks.size != len(self.patterns):
+            raise PMError(-1, "one k per pattern")
+        self.m = np.array([p.m for p in self.patterns], dtype=np.uint32)
+        self.codes = np.ascontiguousarray(np.concatenate([p.codes for p in self.patterns]), dtype=np.uint8)
+        if capacities is None:
+            capacities = [default_capacity(p, k, n) for p, k in zip(self.patterns, self.ks)]
+        self.capacity = np.ascontiguousarray(capacities, dtype=np.uint64)
+        self.out_off = np.zeros(len(self.patterns), dtype=np.uint64)
+        if len(self.patterns) > 1:
+            self.out_off[1:] = np.cumsum(self.capacity)[:-1]
+        self.total_capacity = int(self.capacity.sum())
+
+    def __len__(self):
+        return len(self.patterns)
+
+
+def batch_workspace_bytes(n: int, batch: Batch, config: BatchConfig | None = None) -> int:
+    return int(lib().pm_scan_batch_workspace_bytes(
+        n, len(batch), batch.m.ctypes.data, batch.capacity.ctypes.data,
+        ctypes.byref(config) if config is not None else None))
+
+
+def scan_batch_async(text: Text, batch: Batch, pos, cnt, n_hits, status, ws, win_begin: int = 0,
+                     win_end: int | None = None, config: BatchConfig | None = None, stream=None) -> None:
+    """Enqueue one pm_scan_batch; outputs are device tensors supplied by the caller."""
+    if win_end is None:
+        win_end = UINT64_MAX
+    check(lib().pm_scan_batch(
+        ctypes.c_void_p(text.data.data_ptr()), text.n, len(batch), batch.codes.ctypes.data,
+        batch.m.ctypes.data, batch.ks.ctypes.data, batch.out_off.ctypes.data, batch.capacity.ctypes.data,
+        int(win_begin), int(win_end), ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(cnt.data_ptr()),
+        ctypes.c_void_p(n_hits.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        ctypes.byref(config) if config is not None else None, _stream(stream)))
+
+
+def scan_batch(text: Text, patterns, ks, capacities=None, config: BatchConfig | None = None,
+               stream=None, rerun: bool = True):
+    """Scan many patterns in one batched launch.  Returns a list of
+    (positions, counts) device tensors, one per pattern, each complete: a
+    pattern whose hits did not fit its share of the output is scanned again
+    alone with an exact buffer (unless rerun=False, then it is None)."""
+    import torch
+
+    batch = patterns if isinstance(patterns, Batch) else Batch(patterns, ks, text.n, capacities)
+    dev = text.data.device
+    pos = torch.empty(max(batch.total_capacity, 1), dtype=torch.int64, device=dev)
+    cnt = torch.empty(max(batch.total_capacity, 1), dtype=torch.uint16, device=dev)
+    n_hits = torch.zeros(len(batch), dtype=torch.int64, device=dev)
+    status = torch.zeros(len(batch), dtype=torch.int32, device=dev)
+    ws = torch.empty(batch_workspace_bytes(text.n, batch, config), dtype=torch.uint8, device=dev)
+    scan_batch_async(text, batch, pos, cnt, n_hits, status, ws, config=config, stream=stream)
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    nh = n_hits.cpu().numpy()
+    st = status.cpu().numpy()
+    out = []
+    for i in range(len(batch)):
+        if st[i] == 0:
+            o = int(batch.out_off[i])
+            out.append((pos[o:o + int(nh[i])], cnt[o:o + int(nh[i])]))
+        elif rerun:
+            out.append(scan(text, batch.patterns[i], int(batch.ks[i]), capacity=int(nh[i]) + 1,
+                            stream=stream))
+        else:
+            out.append(None)
+    return out

@@ -128,3 +128,24 @@ def test_sizes():
         assert scan.text_bytes(n) % 16 == 0
         assert scan.workspace_bytes(n) > 0
     assert scan.lib().pm_pattern_bytes(33) == 32
+
+
+def test_expected_hits_closed_forms():
+    """The output-sizing estimate: (n-m+1) * P(count <= k) for uniform bases,
+    checked against closed forms (exact match probability prod |S_j|/4, and
+    k >= m giving every window)."""
+    P = lambda s: scan.Pattern(s)
+    n = 10 ** 6
+    assert scan.expected_hits(P("ACGT"), 0, n) == pytest.approx((n - 3) / 256)
+    assert scan.expected_hits(P("MRN-"), 1, n) == pytest.approx((n - 3) * (0.5 * 0.5 * 1.0))
+    assert scan.expected_hits(P("GATTACA"), 7, n) == pytest.approx(n - 6)
+    # one mismatch allowed over 4 singletons: (1/4)^4 + 4 * (3/4) (1/4)^3
+    assert scan.expected_hits(P("ACGT"), 1, n) == pytest.approx((n - 3) * (1 / 256 + 4 * 0.75 / 64))
+    assert scan.expected_hits(P("ACGT"), 0, 3) == 0.0
+
+
+def test_batch_workspace_grows_with_capacity():
+    b1 = scan.Batch(["ACGT" * 10, "GATTACA"], [2, 1], 10 ** 6, capacities=[100, 100])
+    b2 = scan.Batch(["ACGT" * 10, "GATTACA"], [2, 1], 10 ** 6, capacities=[100000, 100])
+    assert scan.batch_workspace_bytes(10 ** 6, b2) > scan.batch_workspace_bytes(10 ** 6, b1) > 0
+    assert b2.out_off.tolist() == [0, 100000]
