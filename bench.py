@@ -33,9 +33,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # int32 VALU lane-ops/s: CUs x lanes x clock
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("pmscan.hip", "plan.cpp", "plan.hpp"):
+    for f in ("pmscan.hip", "plan.cpp", "plan.hpp", "scan_core.hpp", "batch.hip"):
         with open(os.path.join(ROOT, "paper_1611_06115_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -52,6 +55,19 @@ def measured_traffic(workload: str):
     if t.get("kernel_source_sha") != kernel_source_sha():
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def measured_valu(workload: str):
+    """Executed VALU instructions (x64 lanes) per step from a committed counter
+    run, or None when absent or taken on a different kernel source."""
+    path = os.path.join(PROFILE_DIR, f"scan_{workload}_valu.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return t.get("valu_lane_ops_per_step")
 
 
 def time_steps(fn, steps: int, warmup: int, stream):
@@ -197,12 +213,95 @@ def copy_calibration(gib: float = 1.0, reps: int = 3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def run_batched(args):
+    import numpy as np
+    import torch
+
+    from paper_1611_06115_amd import scan, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    count = args.count or 4096
+    w = synth.batched(n=args.n or 256_000_000, count=count)
+    log(f"[bench] generated {w.n} bases and {count} patterns in {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream()
+    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
+    stream.synchronize()
+    text.check()
+    batch = scan.Batch(w.patterns, w.ks, text.n)
+    cfg = scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0)
+    pos = torch.empty(batch.total_capacity, dtype=torch.int64, device=dev)
+    cnt = torch.empty(batch.total_capacity, dtype=torch.uint16, device=dev)
+    n_hits = torch.zeros(count, dtype=torch.int64, device=dev)
+    status = torch.zeros(count, dtype=torch.int32, device=dev)
+    ws = torch.empty(scan.batch_workspace_bytes(text.n, batch, cfg), dtype=torch.uint8, device=dev)
+    step = lambda: scan.scan_batch_async(text, batch, pos, cnt, n_hits, status, ws, config=cfg)  # noqa
+    ms = time_steps(step, args.steps, args.warmup, stream)
+    nh = n_hits.cpu().numpy()
+    st = status.cpu().numpy()
+    log(f"[bench] {args.steps} steps, {ms:.3f} ms/step, {int(nh.sum())} hits, {int(st.sum())} incomplete")
+    # planted copies must be found
+    found = {}
+    for i in range(count):
+        if st[i] == 0:
+            o = int(batch.out_off[i])
+            found[i] = set(pos[o:o + int(nh[i])].cpu().tolist())
+    missed = [(pi, p) for pi, p, d in w.plants if pi in found and p not in found[pi]]
+    if missed:
+        raise SystemExit(f"planted sites missed: {missed[:5]}")
+    m = batch.m.astype(np.float64)
+    comps = float(((text.n - m + 1).clip(min=0) * m).sum())
+    sec = ms / 1e3
+    valu = measured_valu("batched")
+    result = {
+        "metric": "G base-pattern comparisons/sec",
+        "value": round(comps / sec / 1e9, 1),
+        "unit": "G comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bitwise (exact integer counts)", "data": "synthetic",
+        "config": {"workload": f"batched: n={text.n} i.i.d. GC 0.41, {count} patterns, m ~ U{{16..2048}}, "
+                               f"class density ~ U[0,0.3], k ~ U{{0..8}}, 2 plants each",
+                   "hits": int(nh.sum()), "incomplete": int(st.sum()),
+                   "group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges, "lane_words": cfg.lane_words},
+        "roofline": {"bound": "alu", "achieved": None if valu is None else round(valu / sec / 1e12, 2),
+                     "peak": round(VALU_PEAK_TOPS, 1), "unit": "T int32 VALU lane-ops/s",
+                     "frac": None if valu is None else round(valu / sec / 1e12 / VALU_PEAK_TOPS, 4),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        threads = max(1, min(16, os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        done = 0
+        comps_cpu = 0.0
+        win = 4_000_000
+        for i in range(count):   # patterns in order, one window prefix each, ~10 s in all
+            sets = oracle.parse(w.patterns[i])
+            oracle.scan(w.text, sets, w.ks[i], threads=threads, win_end=win, capacity=1 << 16)
+            comps_cpu += min(win, text.n - len(sets) + 1) * len(sets)
+            done += 1
+            if time.perf_counter() - t0 > 10.0:
+                break
+        dt = time.perf_counter() - t0
+        result["cpu_baseline"] = {"value": round(comps_cpu / dt / 1e9, 3), "unit": "G comparisons/s",
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": f"first {done} patterns, windows [0, {win}) each, {dt:.1f} s"}
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched"])
+    ap.add_argument("--count", type=int, default=None, help="batched: number of patterns")
+    ap.add_argument("--group", type=int, default=None, help="batched: patterns per text tile")
+    ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
+    ap.add_argument("--lane-words", type=int, default=None, help="batched: 4 or 6")
     ap.add_argument("--n", type=int, default=None, help="override the text length")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
@@ -217,7 +316,7 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
               "by text range with an m-1 overlap and no exchange, see the design notes", flush=True)
         raise SystemExit(2)
-    res = run_plain(args)
+    res = run_batched(args) if args.workload == "batched" else run_plain(args)
     print(json.dumps(res), flush=True)
 
 

@@ -140,9 +140,9 @@ pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_
  * ------------------------------------------------------------------------ */
 
 typedef struct {
-    uint32_t group_size;  /* patterns sharing each text tile (1..16); 0 = 4          */
+    uint32_t group_size;  /* patterns sharing each text tile (1..16); 0 = 8          */
     uint32_t sub_ranges;  /* text sub-ranges per pattern group (1..1000); 0 = auto   */
-    uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = 6                 */
+    uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = 4                 */
     uint32_t reserved;
 } pm_batch_config;
 

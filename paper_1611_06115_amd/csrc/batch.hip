@@ -128,36 +128,54 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, const Batch
 
 // Counter depth L of a pattern's filter decides its code path.  Two kernels:
 // WIDE = false takes L <= 4 (k - #'-' <= 15), WIDE = true takes L = 5 or 6,
-// so that the common kernel is not sized for the deepest counters.
-template <int R, bool WIDE>
+// so that the common kernel is not sized for the deepest counters.  A group's
+// patterns share the filter kind EXH, so an item runs one of two pattern
+// loops: singleton filters (which need the mismatch planes) or exhaustive
+// filters (which need the raw planes).
+template <int R, bool EXH, bool WIDE>
 __device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, const BatchPattern& bp, uint32_t sub,
                                                 uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
                                                 uint32_t before) {
-    switch (bp.variant) {
-#define PM_V(E, L) \
-    case (E) * 8 + (L): return pattern_tile<R, L, (E) != 0>(a, bp, sub, T0, wlo, whi, s, before);
-        PM_V(0, 0) PM_V(0, 1) PM_V(0, 2) PM_V(0, 3) PM_V(0, 4)
-        PM_V(1, 0) PM_V(1, 1) PM_V(1, 2) PM_V(1, 3) PM_V(1, 4)
+    switch (bp.variant & 7u) {
+#define PM_V(L) \
+    case L: return pattern_tile<R, L, EXH>(a, bp, sub, T0, wlo, whi, s, before);
+        PM_V(0) PM_V(1) PM_V(2) PM_V(3) PM_V(4)
 #undef PM_V
         default: break;
     }
     if constexpr (WIDE) {
-        switch (bp.variant) {
-            case 5: return pattern_tile<R, 5, false>(a, bp, sub, T0, wlo, whi, s, before);
-            case 6: return pattern_tile<R, 6, false>(a, bp, sub, T0, wlo, whi, s, before);
-            case 13: return pattern_tile<R, 5, true>(a, bp, sub, T0, wlo, whi, s, before);
-            case 14: return pattern_tile<R, 6, true>(a, bp, sub, T0, wlo, whi, s, before);
+        switch (bp.variant & 7u) {
+            case 5: return pattern_tile<R, 5, EXH>(a, bp, sub, T0, wlo, whi, s, before);
+            case 6: return pattern_tile<R, 6, EXH>(a, bp, sub, T0, wlo, whi, s, before);
             default: break;
         }
     }
     return 0;
 }
 
+template <int R, bool EXH, bool WIDE>
+__device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it, uint64_t blo, uint64_t wlo,
+                                         uint64_t whi, uint32_t (&cnt)[kMaxGroup]) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t tile = 64ull * R;
+    for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
+        // text of the tile from its first block (filter windows start at 0)
+        uint4 txt[(R + 2) / 2];
+        const uint32_t g0 = (uint32_t)(T0 >> 1) + lane * (R / 2);
+#pragma unroll
+        for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
+        Lane<R> s;
+        make_lane<R>(txt, EXH ? 0u : 15u, s);
+        for (uint32_t g = 0; g < it.count; ++g) {
+            const BatchPattern& bp = a.pats[it.first + g];
+            cnt[g] += run_pattern<R, EXH, WIDE>(a, bp, it.sub, T0, wlo, whi, s, cnt[g]);
+        }
+    }
+}
+
 template <int R, bool WIDE>
 __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
-    __shared__ uint32_t s_count[TPB / 64][kMaxGroup];
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     while (true) {
         uint32_t item = 0;
         if (lane == 0) item = atomicAdd(a.queue, 1u);
@@ -168,26 +186,18 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
         const uint64_t bhi = blo + a.span_blocks;
         const uint64_t wlo = 32 * blo > a.win_begin ? 32 * blo : a.win_begin;
         const uint64_t whi = 32 * bhi < a.win_end ? 32 * bhi : a.win_end;
-        if (lane < it.count) s_count[wave][lane] = 0;
-        if (wlo < whi) {
-            const uint64_t tile = 64ull * R;
-            for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
-                // text of the tile from its first block (filter windows start at 0)
-                uint4 txt[(R + 2) / 2];
-                const uint32_t g0 = (uint32_t)(T0 >> 1) + lane * (R / 2);
+        // per-pattern running hit counts of this item (wave-uniform)
+        uint32_t cnt[kMaxGroup];
 #pragma unroll
-                for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
-                Lane<R> s;
-                make_lane<R>(txt, 15u, s);
-                for (uint32_t g = 0; g < it.count; ++g) {
-                    const BatchPattern& bp = a.pats[it.first + g];
-                    const uint32_t before = s_count[wave][g];
-                    const uint32_t got = run_pattern<R, WIDE>(a, bp, it.sub, T0, wlo, whi, s, before);
-                    if (lane == 0) s_count[wave][g] = before + got;
-                }
-            }
+        for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
+        if (wlo < whi) {
+            if (a.pats[it.first].variant & 8u) run_item<R, true, WIDE>(a, it, blo, wlo, whi, cnt);
+            else run_item<R, false, WIDE>(a, it, blo, wlo, whi, cnt);
         }
-        if (lane < it.count) a.counts[(uint64_t)a.pats[it.first + lane].index * a.n_sub + it.sub] = s_count[wave][lane];
+#pragma unroll
+        for (int g = 0; g < kMaxGroup; ++g)
+            if ((uint32_t)g < it.count && lane == 0)
+                a.counts[(uint64_t)a.pats[it.first + g].index * a.n_sub + it.sub] = cnt[g];
     }
 }
 
@@ -255,8 +265,8 @@ struct BatchLayout {
 BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, uint64_t win_begin,
                        uint64_t win_end) {
     BatchShape sh;
-    sh.G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 4;
-    sh.R = cfg && cfg->lane_words == 4 ? 4 : 6;
+    sh.G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 8;
+    sh.R = cfg && cfg->lane_words == 6 ? 6 : 4;
     const uint64_t groups = (count + sh.G - 1) / sh.G;
     uint32_t S = cfg && cfg->sub_ranges ? cfg->sub_ranges : 0;
     if (S == 0) {
