@@ -171,6 +171,110 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
                         uint32_t* status_dev, void* ws_dev, uint64_t ws_bytes,
                         const pm_batch_config* cfg, void* stream);
 
+/* ------------------------------------------------------------------------ *
+ * Query server -- a text resident in HBM, pattern queries arriving at any
+ * time, scanned together (continuous batching).  Each query's result is the
+ * pm_scan result of (text, pattern, k) over all windows, bit for bit.
+ *
+ * An engine thread owned by the server admits queries in arrival order while
+ * a slot (config.max_active) and arena memory (hit segments sized from
+ * pm_expected_hits, the pattern image, its share of the batch workspace)
+ * are free.  It scans the text in `chunks` revolving window ranges: one chunk
+ * step is one pm_scan_batch launch over chunk c for every admitted query, so
+ * a query submitted while others are on the GPU joins them at the next step.
+ * After it has been through every chunk, its per-chunk hits are joined in
+ * chunk order (ascending positions) inside the arena and it is complete.  A
+ * chunk whose hits overflow the query's segment is re-scanned with pm_scan
+ * into an exact segment.  Queries wait (they are not refused) while memory
+ * is short; a query that could never fit the arena fails with
+ * PM_ERR_WORKSPACE.
+ * ------------------------------------------------------------------------ */
+
+typedef struct pm_server pm_server;
+
+typedef struct {
+    uint32_t chunks;          /* window ranges per revolution of the text; 0 = 8      */
+    uint32_t max_active;      /* queries scanned together (slots); 0 = 1024           */
+    uint64_t workspace_bytes; /* arena bytes kept for the batch workspace; 0 = 1/4   */
+    pm_batch_config batch;    /* shape of the batched launches; zeros = defaults      */
+} pm_server_config;
+
+#define PM_QUERY_WAITING 0    /* submitted, not admitted yet           */
+#define PM_QUERY_ACTIVE 1     /* admitted, being scanned               */
+#define PM_QUERY_DONE 2       /* result ready in the arena             */
+#define PM_QUERY_FAILED 3     /* see pm_query_info.error               */
+
+typedef struct {
+    int32_t state;            /* PM_QUERY_*                                              */
+    int32_t error;            /* pm_status of a failed query                             */
+    uint64_t n_hits;          /* DONE: number of hits                                    */
+    const int64_t* pos_dev;   /* DONE: n_hits positions, ascending (NULL if none); arena */
+    const uint16_t* cnt_dev;  /* DONE: their mismatch counts; both valid until release   */
+    uint64_t arrival_ns;      /* pm_server_now_ns clock                                  */
+    uint64_t admit_ns;
+    uint64_t complete_ns;
+    uint32_t first_chunk;     /* chunk of its first step                                 */
+    uint32_t reruns;          /* chunks re-scanned after an overflow                     */
+} pm_query_info;
+
+typedef struct {
+    uint64_t steps;           /* chunk steps launched                                    */
+    uint64_t submitted, admitted, completed, failed;
+    uint64_t reruns;
+    uint64_t comparisons;     /* sum over completed queries of (n - m + 1) * m           */
+    uint32_t active, waiting; /* now                                                      */
+    uint32_t peak_active;
+    uint32_t chunks;
+    uint64_t hit_slots;       /* hit slots (10 bytes each) in the arena                  */
+    uint64_t hit_slots_used, hit_slots_peak;
+    uint64_t workspace_bytes;
+} pm_server_stats;
+
+/* Monotonic clock of the server, in nanoseconds. */
+uint64_t pm_server_now_ns(void);
+
+/* Create a server over the encoded text (text_dev, n bases; it must stay
+ * valid and unchanged until pm_server_destroy).  arena_dev/arena_bytes:
+ * caller-owned device memory, 256-byte aligned, used for every buffer of the
+ * server (at least pm_server_min_arena_bytes).  `stream`: the stream of the
+ * chunk steps (a second stream is created for the joins and re-scans; both
+ * are at the default priority).  cfg may be NULL. */
+uint64_t pm_server_min_arena_bytes(uint64_t n, const pm_server_config* cfg);
+pm_status pm_server_create(const void* text_dev, uint64_t n, void* arena_dev, uint64_t arena_bytes,
+                           const pm_server_config* cfg, void* stream, pm_server** out);
+
+/* Submit a query: Table 2 codes (host, copied), length m >= 1, k <= 65535.
+ * arrival_ns: the time the query arrived on pm_server_now_ns's clock (0 =
+ * now); latency is complete_ns - arrival_ns.  Thread-safe. */
+pm_status pm_server_submit(pm_server* srv, const uint8_t* codes, uint32_t m, uint32_t k, uint64_t arrival_ns,
+                           uint64_t* id_out);
+
+/* State of a query (PM_ERR_NOT_FOUND for an unknown or released id). */
+pm_status pm_server_poll(pm_server* srv, uint64_t id, pm_query_info* info);
+
+/* Wait until the query is DONE or FAILED (PM_ERR_BUSY after timeout_ms;
+ * timeout_ms < 0 waits without limit). */
+pm_status pm_server_wait(pm_server* srv, uint64_t id, int64_t timeout_ms, pm_query_info* info);
+
+/* Hand a DONE or FAILED query's memory back to the server; its pointers are
+ * invalid afterwards (the caller must have finished reading them, e.g. by
+ * synchronising the stream of its copy).  PM_ERR_BUSY if not finished. */
+pm_status pm_server_release(pm_server* srv, uint64_t id);
+
+/* Wait until every submitted query is DONE or FAILED (PM_ERR_BUSY after
+ * timeout_ms). */
+pm_status pm_server_drain(pm_server* srv, int64_t timeout_ms);
+
+pm_status pm_server_stats_get(pm_server* srv, pm_server_stats* out);
+
+/* Detail of the error that stopped the engine ("" if none). */
+const char* pm_server_error_detail(pm_server* srv);
+
+/* Stop the engine: GPU work in flight finishes, queries not DONE become
+ * FAILED (PM_ERR_BUSY), and the server is freed (the arena stays the
+ * caller's). */
+pm_status pm_server_destroy(pm_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/pmscan.h"
+#include "batch.hpp"
 #include "plan.hpp"
 #include "scan_core.hpp"
 
@@ -201,33 +202,40 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
     }
 }
 
-// One workgroup per pattern: concatenate its sub-ranges in text order.
+// Workgroups (p, y): concatenate pattern p's sub-ranges in text order, y
+// taking the sub-ranges s = y, y + gridDim.y, ...  Every workgroup of p forms
+// the same offsets from the per-sub-range counts; (p, 0) reports the total
+// and the status.
 __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* gp, const uint32_t* counts,
                                                            uint32_t n_sub, const unsigned long long* staged,
                                                            int64_t* pos, uint16_t* cnt,
                                                            unsigned long long* n_hits, uint32_t* status) {
-    __shared__ unsigned long long s_off[1024];
+    __shared__ unsigned long long s_off[1024 + 1];
     __shared__ uint32_t s_flag;
     const uint32_t p = blockIdx.x;
     const GatherPattern g = gp[p];
+    for (uint32_t s = threadIdx.x; s < n_sub; s += TPB) s_off[s + 1] = counts[(uint64_t)p * n_sub + s];
+    __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long run = 0;
         uint32_t over = 0;
+        s_off[0] = 0;
         for (uint32_t s = 0; s < n_sub; ++s) {
-            const uint32_t c = counts[(uint64_t)p * n_sub + s];
-            s_off[s] = run;
-            run += c;
+            const unsigned long long c = s_off[s + 1];
             if (c > g.cap_sub) over = 1;
+            run += c;
+            s_off[s + 1] = run;
         }
-        s_off[n_sub] = run;
         if (run > g.capacity) over = 1;
-        n_hits[p] = run;
-        status[p] = over;
+        if (blockIdx.y == 0) {
+            n_hits[p] = run;
+            status[p] = over;
+        }
         s_flag = over;
     }
     __syncthreads();
     if (s_flag) return;
-    for (uint32_t s = 0; s < n_sub; ++s) {
+    for (uint32_t s = blockIdx.y; s < n_sub; s += gridDim.y) {
         const uint64_t first = s_off[s];
         const uint32_t c = (uint32_t)(s_off[s + 1] - first);
         const unsigned long long* src = staged + g.stage_off + (uint64_t)s * g.cap_sub;
@@ -255,8 +263,11 @@ struct BatchShape {
     uint64_t span_blocks, wb0;
 };
 
+// Workspace layout.  The descriptor (patterns, gather records, images, work
+// items) comes first and is copied from the host in one piece up to the last
+// item in use; the queue words and the counts are zeroed on the device.
 struct BatchLayout {
-    uint64_t pats, items, images, gather, queue, counts, staged, bytes;
+    uint64_t pats, gather, images, items, queue, counts, staged, bytes;
     std::vector<uint64_t> image_off, stage_off;
     std::vector<uint32_t> cap_sub;
     uint64_t n_items_max;
@@ -286,7 +297,8 @@ BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, u
     return sh;
 }
 
-BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capacity, const BatchShape& sh) {
+BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capacity, const BatchShape& sh,
+                         bool with_images) {
     BatchLayout L;
     L.image_off.resize(count);
     L.stage_off.resize(count);
@@ -295,7 +307,7 @@ BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capa
     uint64_t img = 0, stg = 0;
     for (uint32_t p = 0; p < count; ++p) {
         L.image_off[p] = img;
-        img += (m[p] + 31) / 32;
+        if (with_images) img += (m[p] + 31) / 32;
         const uint64_t c = capacity[p];
         const uint64_t cs = std::min<uint64_t>(c, (2 * c + sh.S - 1) / sh.S + 16);
         L.cap_sub[p] = (uint32_t)std::min<uint64_t>(cs, 0xFFFFFFF0ull);
@@ -305,12 +317,12 @@ BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capa
     uint64_t off = 0;
     L.pats = off;
     off = align256(off + sizeof(BatchPattern) * (uint64_t)count);
-    L.items = off;
-    off = align256(off + sizeof(BatchItem) * L.n_items_max);
     L.gather = off;
     off = align256(off + sizeof(GatherPattern) * (uint64_t)count);
     L.images = off;
     off = align256(off + 16 * img);
+    L.items = off;
+    off = align256(off + sizeof(BatchItem) * L.n_items_max);
     L.queue = off;
     off = align256(off + 8);
     L.counts = off;
@@ -350,46 +362,55 @@ unsigned batch_grid(BatchFn fn, uint64_t items) {
 
 }  // namespace
 
-extern "C" {
+namespace pm {
 
-pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n, double* out) {
-    if (!codes || !out) return set_error(PM_ERR_ARG, "null pointer");
-    for (uint32_t j = 0; j < m; ++j)
-        if (codes[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15");
-    *out = expected_hits(codes, m, k, n);
-    return PM_OK;
-}
-
-uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
-                                       const pm_batch_config* cfg) {
+uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
+                        const pm_batch_config* cfg, bool with_images) {
     if (count == 0 || !m || !capacity) return 256;
     const BatchShape sh = batch_shape(n, count, cfg, 0, n);
-    return batch_layout(count, m, capacity, sh).bytes;
+    return batch_layout(count, m, capacity, sh, with_images).bytes;
 }
 
-pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const uint8_t* codes,
-                        const uint32_t* m, const uint32_t* k, const uint64_t* out_off, const uint64_t* capacity,
-                        uint64_t win_begin, uint64_t win_end, int64_t* pos_dev, uint16_t* cnt_dev,
-                        uint64_t* n_hits_dev, uint32_t* status_dev, void* ws_dev, uint64_t ws_bytes,
-                        const pm_batch_config* cfg, void* stream) {
+uint64_t batch_desc_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
+                          const pm_batch_config* cfg, bool with_images) {
+    if (count == 0 || !m || !capacity) return 256;
+    const BatchShape sh = batch_shape(n, count, cfg, 0, n);
+    return batch_layout(count, m, capacity, sh, with_images).queue;
+}
+
+pm_status batch_run(const BatchCall& c) {
+    const uint32_t count = c.count;
     if (count == 0) return PM_OK;
-    if (!text_dev || !codes || !out_off || !n_hits_dev || !status_dev || !ws_dev)
+    if (!c.text_dev || !c.entries || !c.n_hits_dev || !c.status_dev || !c.ws_dev)
         return set_error(PM_ERR_ARG, "null pointer");
-    pm_status st = check_batch_args(count, m, k, capacity);
-    if (st != PM_OK) return st;
-    if (reinterpret_cast<uintptr_t>(text_dev) % 16 != 0) return set_error(PM_ERR_ARG, "text_dev must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(c.text_dev) % 16 != 0)
+        return set_error(PM_ERR_ARG, "text_dev must be 16-byte aligned");
+    const uint64_t n = c.n;
     if (encoded_text_groups(n) >= (1ull << 32)) return set_error(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
-    for (uint32_t p = 0; p < count; ++p)
-        if (capacity[p] > 0 && (!pos_dev || !cnt_dev)) return set_error(PM_ERR_ARG, "null output with capacity > 0");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::vector<uint32_t> m(count), k(count);
+    std::vector<uint64_t> capacity(count);
+    for (uint32_t p = 0; p < count; ++p) {
+        const BatchEntry& e = c.entries[p];
+        if (!e.codes) return set_error(PM_ERR_ARG, "null pattern codes");
+        m[p] = e.m;
+        k[p] = e.k;
+        capacity[p] = e.capacity;
+        if (e.capacity > 0 && (!c.pos_dev || !c.cnt_dev))
+            return set_error(PM_ERR_ARG, "null output with capacity > 0");
+    }
+    pm_status st = check_batch_args(count, m.data(), k.data(), capacity.data());
+    if (st != PM_OK) return st;
+    const bool with_images = c.images_dev == nullptr;
+    hipStream_t s = c.stream;
+    uint64_t win_begin = c.win_begin, win_end = c.win_end;
     if (win_end > n) win_end = n;
     if (win_begin > win_end) win_begin = win_end;
     // The workspace is laid out for the whole text (full.S sub-ranges per
     // pattern).  A call uses only as many sub-ranges as its window range
     // fills with whole tiles, and gives each the staging of the unused ones.
-    const BatchShape full = batch_shape(n, count, cfg, 0, n);
-    BatchLayout L = batch_layout(count, m, capacity, full);
-    if (ws_bytes < L.bytes)
+    const BatchShape full = batch_shape(n, count, c.cfg, 0, n);
+    BatchLayout L = batch_layout(count, m.data(), capacity.data(), full, with_images);
+    if (c.ws_bytes < L.bytes)
         return set_error(PM_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.bytes) + " bytes");
     BatchShape sh = full;
     {
@@ -403,37 +424,51 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
             L.cap_sub[p] = (uint32_t)std::min<uint64_t>((uint64_t)full.S * L.cap_sub[p] / sh.S, 0xFFFFFFF0ull);
     }
 
+    // the descriptor: staged in the caller's pinned buffer, or a pageable one
+    std::vector<uint8_t> own;
+    uint8_t* desc = c.desc_host;
+    if (desc) {
+        if (c.desc_host_bytes < L.queue) return set_error(PM_ERR_WORKSPACE, "descriptor staging too small");
+    } else {
+        own.assign(L.queue, 0);
+        desc = own.data();
+    }
+    BatchPattern* sorted = reinterpret_cast<BatchPattern*>(desc + L.pats);
+    GatherPattern* gat = reinterpret_cast<GatherPattern*>(desc + L.gather);
+    uint32_t* img_words = reinterpret_cast<uint32_t*>(desc + L.images);
+    BatchItem* items = reinterpret_cast<BatchItem*>(desc + L.items);
+
     // plans, images, groups and queue order on the host
-    std::vector<uint64_t> code_off(count + 1, 0);
-    for (uint32_t p = 0; p < count; ++p) code_off[p + 1] = code_off[p] + m[p];
     std::vector<BatchPattern> pats(count);
-    std::vector<GatherPattern> gat(count);
-    // the image pool occupies [L.images, L.queue) of the descriptor region
-    std::vector<uint32_t> img_words((L.queue - L.images) / 4, 0u);
     std::vector<double> cost(count, 0.0);
     for (uint32_t p = 0; p < count; ++p) {
-        const uint8_t* c = codes + code_off[p];
-        for (uint32_t j = 0; j < m[p]; ++j)
-            if (c[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15 in pattern " + std::to_string(p));
+        const BatchEntry& e = c.entries[p];
+        for (uint32_t j = 0; j < e.m; ++j)
+            if (e.codes[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15 in pattern " + std::to_string(p));
         BatchPattern& bp = pats[p];
         std::memset(&bp, 0, sizeof(bp));
-        bp.plan = build_plan(c, m[p], k[p], 4e-5, /*window_at_zero=*/true);
-        bp.image_off = L.image_off[p];
+        bp.plan = e.plan ? *e.plan : build_plan(e.codes, e.m, e.k, 4e-5, /*window_at_zero=*/true);
+        bp.image_off = with_images ? L.image_off[p] : e.image_off;
         bp.stage_off = L.stage_off[p];
         bp.cap_sub = L.cap_sub[p];
-        bp.nw = m[p] <= n ? n - m[p] + 1 : 0;
+        bp.nw = e.m <= n ? n - e.m + 1 : 0;
         bp.index = p;
         const bool skip = bp.plan.keff < 0 || bp.nw == 0 || bp.nw <= win_begin;
         bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels;
-        build_image(c, m[p], img_words.data() + 4 * L.image_off[p]);
+        if (with_images) {
+            std::memset(img_words + 4 * L.image_off[p], 0, 16ull * ((e.m + 31) / 32));
+            build_image(e.codes, e.m, img_words + 4 * L.image_off[p]);
+        }
         // cost per tile: filter slots, plus a full count per window without a filter
         cost[p] = skip ? 0.0
                        : (bp.plan.n_slots > 0 || bp.plan.exhaustive ? 8.0 + bp.plan.n_slots
                                                                     : 8.0 + 32.0 * 10.0 * bp.plan.nchunks);
-        gat[p].stage_off = L.stage_off[p];
-        gat[p].out_off = out_off[p];
-        gat[p].capacity = capacity[p];
-        gat[p].cap_sub = L.cap_sub[p];
+        GatherPattern& g = gat[p];
+        std::memset(&g, 0, sizeof(g));
+        g.stage_off = L.stage_off[p];
+        g.out_off = e.out_off;
+        g.capacity = e.capacity;
+        g.cap_sub = L.cap_sub[p];
     }
     // groups: same variant, similar cost; items: (group, sub-range), costly first
     std::vector<uint32_t> order(count);
@@ -442,7 +477,6 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
         if (pats[x].variant != pats[y].variant) return pats[x].variant < pats[y].variant;
         return cost[x] > cost[y];
     });
-    std::vector<BatchPattern> sorted(count);
     for (uint32_t i = 0; i < count; ++i) sorted[i] = pats[order[i]];
     struct Group {
         uint32_t first, count;
@@ -451,47 +485,41 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
     std::vector<Group> groups;
     for (uint32_t i = 0; i < count;) {
         uint32_t j = i;
-        double c = 0;
-        while (j < count && j - i < sh.G && sorted[j].variant == sorted[i].variant) c += cost[order[j++]];
-        groups.push_back({i, j - i, c});
+        double cs = 0;
+        while (j < count && j - i < sh.G && sorted[j].variant == sorted[i].variant) cs += cost[order[j++]];
+        groups.push_back({i, j - i, cs});
         i = j;
     }
     std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.cost > y.cost; });
     // common items first, then the items of patterns with 5 or 6 counter levels
-    std::vector<BatchItem> items;
-    items.reserve(groups.size() * sh.S);
+    uint64_t n_items = 0, n_common = 0;
     auto is_wide = [&](const Group& g) { return (sorted[g.first].variant & 7u) >= 5u; };
-    for (int pass = 0; pass < 2; ++pass)
+    for (int pass = 0; pass < 2; ++pass) {
         for (const Group& g : groups) {
             if (g.cost == 0.0 || is_wide(g) != (pass == 1)) continue;
-            for (uint32_t sub = 0; sub < sh.S; ++sub) items.push_back({g.first, g.count, sub, 0});
+            if (n_items + sh.S > L.n_items_max) return set_error(PM_ERR_ARG, "internal: too many work items");
+            for (uint32_t sub = 0; sub < sh.S; ++sub) items[n_items++] = {g.first, g.count, sub, 0};
         }
-    size_t n_common = 0;
-    while (n_common < items.size() && (sorted[items[n_common].first].variant & 7u) < 5u) ++n_common;
-    if (items.size() > L.n_items_max) return set_error(PM_ERR_ARG, "internal: too many work items");
+        if (pass == 0) n_common = n_items;
+    }
 
-    uint8_t* ws = reinterpret_cast<uint8_t*>(ws_dev);
+    uint8_t* ws = reinterpret_cast<uint8_t*>(c.ws_dev);
     hipError_t e;
-    // one copy of the descriptor region (patterns .. images)
-    std::vector<uint8_t> desc(L.queue, 0);
-    std::memcpy(desc.data() + L.pats, sorted.data(), sizeof(BatchPattern) * count);
-    if (!items.empty()) std::memcpy(desc.data() + L.items, items.data(), sizeof(BatchItem) * items.size());
-    std::memcpy(desc.data() + L.gather, gat.data(), sizeof(GatherPattern) * count);
-    std::memcpy(desc.data() + L.images, img_words.data(), 4 * img_words.size());
-    if ((e = hipMemcpyAsync(ws, desc.data(), desc.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+    // one copy of the descriptor up to the last item in use
+    const uint64_t desc_used = L.items + sizeof(BatchItem) * n_items;
+    if ((e = hipMemcpyAsync(ws, desc, desc_used, hipMemcpyHostToDevice, s)) != hipSuccess)
         return set_error(PM_ERR_HIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
     // queue and per-(pattern, sub-range) counts start at zero (patterns that
     // get no work item keep zero counts)
-    fill_zero_kernel<<<1024, TPB, 0, s>>>(reinterpret_cast<uint32_t*>(ws + L.queue),
-                                          (L.staged - L.queue) / 4);
+    fill_zero_kernel<<<1024, TPB, 0, s>>>(reinterpret_cast<uint32_t*>(ws + L.queue), (L.staged - L.queue) / 4);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
 
     BatchArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.text4 = reinterpret_cast<const uint4*>(text_dev);
+    a.text4 = reinterpret_cast<const uint4*>(c.text_dev);
     a.n4_last = (uint32_t)(encoded_text_groups(n) - 1);
-    a.n_items = (uint32_t)items.size();
-    a.images = reinterpret_cast<const uint4*>(ws + L.images);
+    a.images = with_images ? reinterpret_cast<const uint4*>(ws + L.images)
+                           : reinterpret_cast<const uint4*>(c.images_dev);
     a.pats = reinterpret_cast<const BatchPattern*>(ws + L.pats);
     a.items = reinterpret_cast<const BatchItem*>(ws + L.items);
     a.staged = reinterpret_cast<unsigned long long*>(ws + L.staged);
@@ -510,20 +538,75 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
         fn<<<batch_grid(fn, n_common), TPB, 0, s>>>(a);
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }
-    if (items.size() > n_common) {
+    if (n_items > n_common) {
         BatchFn fn = sh.R == 4 ? batch_kernel<4, true> : batch_kernel<6, true>;
         BatchArgs w = a;
         w.items = a.items + n_common;
-        w.n_items = (uint32_t)(items.size() - n_common);
+        w.n_items = (uint32_t)(n_items - n_common);
         w.queue = a.queue + 1;
         fn<<<batch_grid(fn, w.n_items), TPB, 0, s>>>(w);
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }
-    batch_gather_kernel<<<count, TPB, 0, s>>>(reinterpret_cast<const GatherPattern*>(ws + L.gather), a.counts, sh.S,
-                                              a.staged, pos_dev, cnt_dev,
-                                              reinterpret_cast<unsigned long long*>(n_hits_dev), status_dev);
+    // patterns with large outputs are gathered by up to 16 workgroups each
+    uint64_t max_cap = 0;
+    for (uint32_t p = 0; p < count; ++p) max_cap = std::max<uint64_t>(max_cap, capacity[p]);
+    const uint32_t gy = (uint32_t)std::min<uint64_t>({16, sh.S, std::max<uint64_t>(1, max_cap >> 16)});
+    batch_gather_kernel<<<dim3(count, gy), TPB, 0, s>>>(reinterpret_cast<const GatherPattern*>(ws + L.gather),
+                                                        a.counts, sh.S, a.staged, c.pos_dev, c.cnt_dev,
+                                                        reinterpret_cast<unsigned long long*>(c.n_hits_dev),
+                                                        c.status_dev);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     return PM_OK;
+}
+
+}  // namespace pm
+
+extern "C" {
+
+pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_t n, double* out) {
+    if (!codes || !out) return set_error(PM_ERR_ARG, "null pointer");
+    for (uint32_t j = 0; j < m; ++j)
+        if (codes[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15");
+    *out = expected_hits(codes, m, k, n);
+    return PM_OK;
+}
+
+uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
+                                       const pm_batch_config* cfg) {
+    return batch_ws_bytes(n, count, m, capacity, cfg, true);
+}
+
+pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const uint8_t* codes,
+                        const uint32_t* m, const uint32_t* k, const uint64_t* out_off, const uint64_t* capacity,
+                        uint64_t win_begin, uint64_t win_end, int64_t* pos_dev, uint16_t* cnt_dev,
+                        uint64_t* n_hits_dev, uint32_t* status_dev, void* ws_dev, uint64_t ws_bytes,
+                        const pm_batch_config* cfg, void* stream) {
+    if (count == 0) return PM_OK;
+    if (!codes || !out_off) return set_error(PM_ERR_ARG, "null pointer");
+    pm_status st = check_batch_args(count, m, k, capacity);
+    if (st != PM_OK) return st;
+    std::vector<BatchEntry> entries(count);
+    uint64_t off = 0;
+    for (uint32_t p = 0; p < count; ++p) {
+        entries[p] = {codes + off, m[p], k[p], nullptr, 0, out_off[p], capacity[p]};
+        off += m[p];
+    }
+    BatchCall c;
+    c.text_dev = text_dev;
+    c.n = n;
+    c.count = count;
+    c.entries = entries.data();
+    c.win_begin = win_begin;
+    c.win_end = win_end;
+    c.pos_dev = pos_dev;
+    c.cnt_dev = cnt_dev;
+    c.n_hits_dev = n_hits_dev;
+    c.status_dev = status_dev;
+    c.ws_dev = ws_dev;
+    c.ws_bytes = ws_bytes;
+    c.cfg = cfg;
+    c.stream = reinterpret_cast<hipStream_t>(stream);
+    return batch_run(c);
 }
 
 }  // extern "C"

@@ -51,6 +51,17 @@ def lib():
             "pm_scan_batch_workspace_bytes": ([u64, u32, vp, vp, vp], u64),
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
                               i32),
+            "pm_server_now_ns": ([], u64),
+            "pm_server_min_arena_bytes": ([u64, vp], u64),
+            "pm_server_create": ([vp, u64, vp, u64, vp, vp, vp], i32),
+            "pm_server_submit": ([vp, vp, u32, u32, u64, vp], i32),
+            "pm_server_poll": ([vp, u64, vp], i32),
+            "pm_server_wait": ([vp, u64, ctypes.c_int64, vp], i32),
+            "pm_server_release": ([vp, u64], i32),
+            "pm_server_drain": ([vp, ctypes.c_int64], i32),
+            "pm_server_stats_get": ([vp, vp], i32),
+            "pm_server_error_detail": ([vp], ctypes.c_char_p),
+            "pm_server_destroy": ([vp], i32),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)

@@ -399,3 +399,12 @@ def poisson_arrivals(rate: float, duration: float, seed: int = SEED0 + 4) -> np.
         u = d.uniform(0, est)
         t = np.cumsum(-np.log1p(-u) / rate)
     return t[t < duration]
+
+
+def served(n: int = 3_100_000_000, count: int = 20000, text: np.ndarray | None = None) -> Workload:
+    """The genome-scale text with the query pool planted in it (one copy per
+    query, d ~ U{0..k}, in its own text segment), before it is made resident."""
+    g = genome(n, text=text)
+    pats, ks = query_pool(count)
+    plants = plant_pool(g.text, pats, ks)
+    return Workload("served", g.seed, n, g.text, pats, ks, plants)
