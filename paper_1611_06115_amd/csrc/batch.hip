@@ -47,7 +47,7 @@ struct BatchPattern {
     uint32_t cap_sub;     // staged hits per sub-range
     uint32_t variant;     // exhaustive << 3 | levels, or kSkip
     uint32_t index;       // the caller's index of the pattern
-    uint32_t pad_[3];
+    uint32_t pad_[1];
 };
 static_assert(sizeof(BatchPattern) % 16 == 0, "BatchPattern must keep 16-byte alignment");
 

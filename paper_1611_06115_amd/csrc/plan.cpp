@@ -212,14 +212,47 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
         while ((1u << L) < K) ++L;
         p.levels = L;
         p.init = (1u << L) - K;
-        uint32_t s = 0;
-        for (uint32_t j = 32 * best_fw; j < std::min(m, 32 * best_fw + 64) && s < J; ++j) {
+        // The J singleton positions, taken class by class: class = (base c,
+        // word q of the filter window), so that a set of up to 4 slots shares
+        // one mismatch plane and one word offset and differs only in the shift
+        // r.  Full sets first, then the largest remainders.
+        std::vector<uint32_t> cls[8];
+        for (uint32_t j = 32 * best_fw; j < std::min(m, 32 * best_fw + 64); ++j) {
             if (!is_single(j)) continue;
             const uint32_t rel = j - 32 * best_fw;
             const unsigned base = static_cast<unsigned>(__builtin_ctz(~mm[j] & 15u));
-            p.slot[s++] = static_cast<uint16_t>(base | ((rel >> 5) << 2) | ((rel & 31u) << 3));
-            p.singles |= 1u << base;
+            cls[base | ((rel >> 5) << 2)].push_back(rel & 31u);
         }
+        uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        uint32_t left = J, n_sets = 0;
+        auto add_set = [&](uint32_t cq, uint32_t cnt) {
+            if (2 * n_sets + 1 >= static_cast<uint32_t>(kMaxSlots)) {  // never reached: J/4 + 8 sets at most
+                left = 0;
+                return;
+            }
+            uint32_t w = cq | (cnt << 3);
+            for (uint32_t u = 0; u < cnt; ++u) w |= cls[cq][used[cq] + u] << (6 + 5 * u);
+            used[cq] += cnt;
+            left -= cnt;
+            p.slot[2 * n_sets] = static_cast<uint16_t>(w & 0xFFFFu);
+            p.slot[2 * n_sets + 1] = static_cast<uint16_t>(w >> 16);
+            ++n_sets;
+            p.singles |= 1u << (cq & 3u);
+        };
+        for (uint32_t cq = 0; cq < 8 && left >= 4; ++cq)
+            while (cls[cq].size() - used[cq] >= 4 && left >= 4) add_set(cq, 4);
+        p.n_groups = n_sets / 2;
+        while (left > 0) {
+            uint32_t best = 8, most = 0;
+            for (uint32_t cq = 0; cq < 8; ++cq)
+                if (cls[cq].size() - used[cq] > most) {
+                    most = static_cast<uint32_t>(cls[cq].size()) - used[cq];
+                    best = cq;
+                }
+            if (best == 8) break;  // cannot happen: J <= singleton positions of the window
+            add_set(best, std::min<uint32_t>({most, left, 4u}));
+        }
+        p.n_sets = n_sets;
     }
     return p;
 }

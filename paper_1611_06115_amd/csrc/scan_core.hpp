@@ -51,10 +51,33 @@ __device__ __forceinline__ void single_words(const Lane<R>& s, uint32_t r, uint3
     for (int i = 0; i < R; ++i) X[i] = align(s.P[C][i + Q + 1], s.P[C][i + Q], r);
 }
 
+// Singleton-filter set (c | q << 2 | 4 << 3 | r_u << (6 + 5u)): the
+// mismatch words of 4 positions of the same base c and word q, shifts r_u.
+// One uniform dispatch per set.
+template <int C, int Q, int R>
+__device__ __forceinline__ void set_words_cq(const Lane<R>& s, uint32_t w, uint32_t (&X)[4][R]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) single_words<C, Q, R>(s, (w >> (6 + 5 * u)) & 31u, X[u]);
+}
+
 template <int R>
-__device__ __forceinline__ void single_slot(uint32_t slot, const Lane<R>& s, uint32_t (&X)[R]) {
-    const uint32_t r = slot >> 3;
-    switch (slot & 7u) {
+__device__ __forceinline__ void single_set(uint32_t w, const Lane<R>& s, uint32_t (&X)[4][R]) {
+    switch (w & 7u) {
+        case 0: set_words_cq<0, 0, R>(s, w, X); break;
+        case 1: set_words_cq<1, 0, R>(s, w, X); break;
+        case 2: set_words_cq<2, 0, R>(s, w, X); break;
+        case 3: set_words_cq<3, 0, R>(s, w, X); break;
+        case 4: set_words_cq<0, 1, R>(s, w, X); break;
+        case 5: set_words_cq<1, 1, R>(s, w, X); break;
+        case 6: set_words_cq<2, 1, R>(s, w, X); break;
+        default: set_words_cq<3, 1, R>(s, w, X); break;
+    }
+}
+
+// One singleton position (class cq = c | q << 2, shift r): for the tail sets.
+template <int R>
+__device__ __forceinline__ void single_slot(uint32_t cq, uint32_t r, const Lane<R>& s, uint32_t (&X)[R]) {
+    switch (cq & 7u) {
         case 0: single_words<0, 0, R>(s, r, X); break;
         case 1: single_words<1, 0, R>(s, r, X); break;
         case 2: single_words<2, 0, R>(s, r, X); break;
@@ -221,7 +244,9 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
     }
 
     // ---- filter ---------------------------------------------------------------
-    if (p.n_slots > 0) {
+    // groups of 8 slots into the counters: a full-adder tree per group (pairs
+    // into level 0, their carries pairwise into level 1, ...)
+    if constexpr (EXH) {
         const uint4* groups = reinterpret_cast<const uint4*>(p.slot);  // 8 slots per 16 bytes
         for (uint32_t g = 0; g < p.n_slots; g += 8) {
             const uint4 gw = groups[g >> 3];
@@ -232,24 +257,42 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
 #pragma unroll
                 for (int pr = 0; pr < 2; ++pr) {
                     const uint32_t w = gv[2 * half + pr];  // slots u and u+1
-                    if constexpr (EXH) {
-                        general_slot<R>(w & 0xFFFFu, s, xa);
-                        general_slot<R>(w >> 16, s, xb);
-                    } else {
-                        single_slot<R>(w & 0xFFFFu, s, xa);
-                        single_slot<R>(w >> 16, s, xb);
-                    }
-                    if constexpr (L == 0) {
-#pragma unroll
-                        for (int i = 0; i < R; ++i) C.dead[i] = or3(C.dead[i], xa[i], xb[i]);
-                    } else {
-                        add2<0, R, L>(C, xa, xb, pr == 0 ? c0a : c0b);
-                    }
+                    general_slot<R>(w & 0xFFFFu, s, xa);
+                    general_slot<R>(w >> 16, s, xb);
+                    add2<0, R, L>(C, xa, xb, pr == 0 ? c0a : c0b);
                 }
                 add2<1, R, L>(C, c0a, c0b, half == 0 ? c1a : c1b);
             }
             add2<2, R, L>(C, c1a, c1b, c2);
             if constexpr (L >= 3) add1<3, R, L>(C, c2);
+        }
+    } else {
+        // groups: two full sets each
+        const uint2* groups = reinterpret_cast<const uint2*>(p.slot);  // 2 sets per 8 bytes
+        for (uint32_t g = 0; g < p.n_groups; ++g) {
+            const uint2 gw = groups[g];
+            uint32_t X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
+            single_set<R>(gw.x, s, X);
+            add2<0, R, L>(C, X[0], X[1], c0a);
+            add2<0, R, L>(C, X[2], X[3], c0b);
+            add2<1, R, L>(C, c0a, c0b, c1a);
+            single_set<R>(gw.y, s, X);
+            add2<0, R, L>(C, X[0], X[1], c0a);
+            add2<0, R, L>(C, X[2], X[3], c0b);
+            add2<1, R, L>(C, c0a, c0b, c1b);
+            add2<2, R, L>(C, c1a, c1b, c2);
+            if constexpr (L >= 3) add1<3, R, L>(C, c2);
+        }
+        // tail: the remaining sets, one position at a time
+        const uint32_t* words = reinterpret_cast<const uint32_t*>(p.slot);
+        for (uint32_t t = 2 * p.n_groups; t < p.n_sets; ++t) {
+            const uint32_t w = words[t];
+            const uint32_t cnt = (w >> 3) & 7u;
+            for (uint32_t u = 0; u < cnt; ++u) {
+                uint32_t X[R];
+                single_slot<R>(w, (w >> (6 + 5 * u)) & 31u, s, X);
+                add1<0, R, L>(C, X);
+            }
         }
     }
 
