@@ -33,7 +33,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # int32 VALU lane-ops/s: CUs x lanes x clock
+VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # int32 VALU lane-ops/s: CUs x lanes per clock x clock
 
 
 def kernel_source_sha() -> str:
@@ -230,7 +230,19 @@ def run_batched(args):
     stream.synchronize()
     text.check()
     batch = scan.Batch(w.patterns, w.ks, text.n)
-    cfg = scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0)
+    tuned = None
+    if args.group is None and args.sub is None and args.lane_words is None:
+        from paper_1611_06115_amd import autotune
+
+        t0 = time.perf_counter()
+        tr = autotune.tune(text, batch)
+        cfg = tr.config
+        tuned = {"group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges, "lane_words": cfg.lane_words,
+                 "cached": tr.cached, "sample_windows": tr.sample_windows, "sample_ms": tr.timings,
+                 "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] autotuned batch shape {tuned}")
+    else:
+        cfg = scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0)
     pos = torch.empty(batch.total_capacity, dtype=torch.int64, device=dev)
     cnt = torch.empty(batch.total_capacity, dtype=torch.uint16, device=dev)
     n_hits = torch.zeros(count, dtype=torch.int64, device=dev)
@@ -264,7 +276,8 @@ def run_batched(args):
         "config": {"workload": f"batched: n={text.n} i.i.d. GC 0.41, {count} patterns, m ~ U{{16..2048}}, "
                                f"class density ~ U[0,0.3], k ~ U{{0..8}}, 2 plants each",
                    "hits": int(nh.sum()), "incomplete": int(st.sum()),
-                   "group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges, "lane_words": cfg.lane_words},
+                   "group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges, "lane_words": cfg.lane_words,
+                   "autotune": tuned},
         "roofline": {"bound": "alu", "achieved": None if valu is None else round(valu / sec / 1e12, 2),
                      "peak": round(VALU_PEAK_TOPS, 1), "unit": "T int32 VALU lane-ops/s",
                      "frac": None if valu is None else round(valu / sec / 1e12 / VALU_PEAK_TOPS, 4),

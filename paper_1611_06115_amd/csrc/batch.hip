@@ -18,6 +18,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pmscan.h"
@@ -439,36 +440,51 @@ pm_status batch_run(const BatchCall& c) {
     BatchItem* items = reinterpret_cast<BatchItem*>(desc + L.items);
 
     // plans, images, groups and queue order on the host
+    for (uint32_t p = 0; p < count; ++p)
+        for (uint32_t j = 0; j < c.entries[p].m; ++j)
+            if (c.entries[p].codes[j] > 15)
+                return set_error(PM_ERR_SYMBOL, "pattern code above 15 in pattern " + std::to_string(p));
     std::vector<BatchPattern> pats(count);
     std::vector<double> cost(count, 0.0);
-    for (uint32_t p = 0; p < count; ++p) {
-        const BatchEntry& e = c.entries[p];
-        for (uint32_t j = 0; j < e.m; ++j)
-            if (e.codes[j] > 15) return set_error(PM_ERR_SYMBOL, "pattern code above 15 in pattern " + std::to_string(p));
-        BatchPattern& bp = pats[p];
-        std::memset(&bp, 0, sizeof(bp));
-        bp.plan = e.plan ? *e.plan : build_plan(e.codes, e.m, e.k, 4e-5, /*window_at_zero=*/true);
-        bp.image_off = with_images ? L.image_off[p] : e.image_off;
-        bp.stage_off = L.stage_off[p];
-        bp.cap_sub = L.cap_sub[p];
-        bp.nw = e.m <= n ? n - e.m + 1 : 0;
-        bp.index = p;
-        const bool skip = bp.plan.keff < 0 || bp.nw == 0 || bp.nw <= win_begin;
-        bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels;
-        if (with_images) {
-            std::memset(img_words + 4 * L.image_off[p], 0, 16ull * ((e.m + 31) / 32));
-            build_image(e.codes, e.m, img_words + 4 * L.image_off[p]);
+    auto prepare = [&](uint32_t p0, uint32_t p1) {
+        for (uint32_t p = p0; p < p1; ++p) {
+            const BatchEntry& e = c.entries[p];
+            BatchPattern& bp = pats[p];
+            std::memset(&bp, 0, sizeof(bp));
+            bp.plan = e.plan ? *e.plan : build_plan(e.codes, e.m, e.k, 4e-5, /*window_at_zero=*/true);
+            bp.image_off = with_images ? L.image_off[p] : e.image_off;
+            bp.stage_off = L.stage_off[p];
+            bp.cap_sub = L.cap_sub[p];
+            bp.nw = e.m <= n ? n - e.m + 1 : 0;
+            bp.index = p;
+            const bool skip = bp.plan.keff < 0 || bp.nw == 0 || bp.nw <= win_begin;
+            bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels;
+            if (with_images) build_image(e.codes, e.m, img_words + 4 * L.image_off[p]);
+            // cost per tile: filter slots, plus a full count per window without a filter
+            cost[p] = skip ? 0.0
+                           : (bp.plan.n_slots > 0 || bp.plan.exhaustive ? 8.0 + bp.plan.n_slots
+                                                                        : 8.0 + 32.0 * 10.0 * bp.plan.nchunks);
+            GatherPattern& g = gat[p];
+            std::memset(&g, 0, sizeof(g));
+            g.stage_off = L.stage_off[p];
+            g.out_off = e.out_off;
+            g.capacity = e.capacity;
+            g.cap_sub = L.cap_sub[p];
         }
-        // cost per tile: filter slots, plus a full count per window without a filter
-        cost[p] = skip ? 0.0
-                       : (bp.plan.n_slots > 0 || bp.plan.exhaustive ? 8.0 + bp.plan.n_slots
-                                                                    : 8.0 + 32.0 * 10.0 * bp.plan.nchunks);
-        GatherPattern& g = gat[p];
-        std::memset(&g, 0, sizeof(g));
-        g.stage_off = L.stage_off[p];
-        g.out_off = e.out_off;
-        g.capacity = e.capacity;
-        g.cap_sub = L.cap_sub[p];
+    };
+    // large batches are prepared by several host threads, in disjoint ranges
+    uint64_t work = 0;
+    for (uint32_t p = 0; p < count; ++p) work += c.entries[p].m + 64;
+    const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const uint32_t nt = (uint32_t)std::min<uint64_t>({hw, count, std::max<uint64_t>(1, work >> 17)});
+    if (nt <= 1) {
+        prepare(0, count);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve(nt);
+        for (uint32_t t = 0; t < nt; ++t)
+            th.emplace_back(prepare, (uint32_t)((uint64_t)count * t / nt), (uint32_t)((uint64_t)count * (t + 1) / nt));
+        for (auto& x : th) x.join();
     }
     // groups: same variant, similar cost; items: (group, sub-range), costly first
     std::vector<uint32_t> order(count);

@@ -58,15 +58,33 @@ uint32_t prime_product(unsigned code) {
     return prod;
 }
 
-unsigned mismatch_mask(unsigned code) {
-    // Pair value L[(p << 2) | t] = 0 iff the text prime divides the class
-    // product (the "modular arithmetic" of Sect. 2.3).
+namespace {
+
+// Pair value L[(p << 2) | t] = 0 iff the text prime divides the class
+// product (the "modular arithmetic" of Sect. 2.3).
+unsigned derive_mismatch_mask(unsigned code) {
     const uint32_t prod = prime_product(code);
     unsigned mm = 0;
     for (int t = 0; t < 4; ++t)
         if (prod % kPrime[t] != 0) mm |= 1u << t;
     return mm;
 }
+
+// The 16 rows of Table 3 as 4-bit masks, derived once from the primes.
+struct MaskTable {
+    uint8_t row[16];
+    MaskTable() {
+        for (unsigned c = 0; c < 16; ++c) row[c] = static_cast<uint8_t>(derive_mismatch_mask(c));
+    }
+};
+const MaskTable& mask_table() {
+    static const MaskTable t;
+    return t;
+}
+
+}  // namespace
+
+unsigned mismatch_mask(unsigned code) { return mask_table().row[code & 15u]; }
 
 int parse_pattern(const char* s, uint64_t len, std::vector<uint8_t>& codes, std::string& err) {
     codes.clear();
@@ -108,12 +126,18 @@ int parse_pattern(const char* s, uint64_t len, std::vector<uint8_t>& codes, std:
 }
 
 void build_image(const uint8_t* codes, uint32_t m, uint32_t* out) {
-    const uint32_t nchunks = (m + 31) / 32;
-    std::memset(out, 0, sizeof(uint32_t) * 4 * nchunks);
-    for (uint32_t j = 0; j < m; ++j) {
-        const unsigned mm = mismatch_mask(codes[j]);
-        for (int t = 0; t < 4; ++t)
-            if (mm >> t & 1u) out[4 * (j / 32) + t] |= 1u << (j % 32);
+    const uint8_t* row = mask_table().row;
+    for (uint32_t c = 0; 32 * c < m; ++c) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        const uint32_t end = std::min<uint32_t>(32, m - 32 * c);
+        for (uint32_t b = 0; b < end; ++b) {
+            const uint32_t mm = row[codes[32 * c + b] & 15u];
+            w[0] |= (mm & 1u) << b;
+            w[1] |= (mm >> 1 & 1u) << b;
+            w[2] |= (mm >> 2 & 1u) << b;
+            w[3] |= (mm >> 3 & 1u) << b;
+        }
+        std::memcpy(out + 4 * c, w, sizeof(w));
     }
 }
 
@@ -125,8 +149,9 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
     p.nchunks = (m + 31) / 32;
     std::vector<unsigned> mm(m);
     uint32_t n_dash = 0;
+    const uint8_t* row = mask_table().row;
     for (uint32_t j = 0; j < m; ++j) {
-        mm[j] = mismatch_mask(codes[j]);
+        mm[j] = row[codes[j] & 15u];
         if (mm[j] == 15u) ++n_dash;
     }
     p.n_dash = n_dash;

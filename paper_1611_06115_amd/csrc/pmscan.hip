@@ -25,9 +25,6 @@
 //      without a sort.
 #include <hip/hip_runtime.h>
 
-#ifndef PMSCAN_PREFETCH
-#define PMSCAN_PREFETCH 1
-#endif
 
 #include <cstdint>
 #include <cstdio>
@@ -251,7 +248,6 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t nw = gridDim.x * (TPB / 64);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
-#if PMSCAN_PREFETCH
     // the text of the wave's next tile is loaded while this one is computed
     uint4 nxt[(R + 2) / 2];
     uint32_t tile = blockIdx.x * (TPB / 64) + wave;
@@ -263,13 +259,6 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
 #pragma unroll
         for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = nxt[u];
         if (tile + nw < a.n_tiles) load_tile_text<R>(a, p, tile_first_block(a, tile + nw, R), nxt);
-#else
-    for (uint32_t tile = blockIdx.x * (TPB / 64) + wave; tile < a.n_tiles; tile += nw) {
-        const uint64_t T0 = tile_first_block(a, tile, R);
-        const uint64_t B = T0 + (uint64_t)lane * R;
-        uint4 txt[(R + 2) / 2];
-        load_tile_text<R>(a, p, T0, txt);
-#endif
         Counters<R, L> C;
         uint32_t hit[R], nh;
         Lane<R> s;
@@ -410,7 +399,7 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
 }
 
 #ifndef PMSCAN_LANE_WORDS
-#define PMSCAN_LANE_WORDS 6
+#define PMSCAN_LANE_WORDS 4
 #endif
 constexpr int kR = PMSCAN_LANE_WORDS;  // lane words (32 windows each) per lane
 
