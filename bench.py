@@ -57,9 +57,10 @@ def measured_traffic(workload: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def measured_valu(workload: str):
-    """Executed VALU instructions (x64 lanes) per step from a committed counter
-    run, or None when absent or taken on a different kernel source."""
+def valu_profile(workload: str):
+    """The committed VALU counter run of a workload ({"config": launch shape,
+    "valu_lane_ops_per_launch": ...}), or None when absent or taken on a
+    different kernel source."""
     path = os.path.join(PROFILE_DIR, f"scan_{workload}_valu.json")
     if not os.path.exists(path):
         return None
@@ -67,23 +68,39 @@ def measured_valu(workload: str):
         t = json.load(f)
     if t.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return t.get("valu_lane_ops_per_step")
+    return t
 
 
-def time_steps(fn, steps: int, warmup: int, stream):
+def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
+    """Mean ms per step over `steps` timed steps (HIP events on `stream`).
+    With kernel=True also the mean duration of the scan's main kernel, from
+    a pair of events the library records around that launch in every step."""
     import torch
+
+    from paper_1611_06115_amd import scan
 
     for _ in range(warmup):
         fn()
+    pairs = []
+    if kernel:
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        for a, b in pairs:  # creates the events
+            a.record(stream)
+            b.record(stream)
     stream.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(steps):
+    for i in range(steps):
+        if kernel:
+            scan.time_next_scan(*pairs[i])
         fn()
     e1.record(stream)
     e1.synchronize()
-    return e0.elapsed_time(e1) / steps
+    step_ms = e0.elapsed_time(e1) / steps
+    if not kernel:
+        return step_ms
+    return step_ms, sum(a.elapsed_time(b) for a, b in pairs) / steps
 
 
 def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0):
@@ -156,9 +173,9 @@ def run_plain(args):
     m = pat.m
     ws = scan.Workspace(dev, text.n, capacity=1 << 20)
     step = lambda: scan.scan_async(text, pat, k, ws)  # noqa: E731
-    ms = time_steps(step, args.steps, args.warmup, stream)
+    ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True)
     hits = int(ws.n_hits.item())
-    log(f"[bench] {args.steps} steps, {ms:.4f} ms/step, {hits} hits")
+    log(f"[bench] {args.steps} steps, {ms:.4f} ms/step (count kernel {kern_ms:.4f} ms), {hits} hits")
 
     # planted copies within the budget must all be reported
     pos = ws.pos[:min(hits, ws.capacity)].cpu().numpy()
@@ -171,8 +188,10 @@ def run_plain(args):
     nw = text.n - m + 1
     comps = nw * m
     sec = ms / 1e3
-    algo_bytes = 0.25 * text.n + 10.0 * hits + pat.image(dev).numel() * 4
-    achieved = algo_bytes / sec / 1e9
+    # algorithmic bytes of the count kernel (one launch): the encoded text once,
+    # the staged hits, the pattern image
+    algo_bytes = 0.25 * text.n + 8.0 * hits + pat.image(dev).numel() * 4
+    achieved = algo_bytes / (kern_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload)
     result = {
         "metric": "G base-pattern comparisons/sec",
@@ -231,7 +250,15 @@ def run_batched(args):
     text.check()
     batch = scan.Batch(w.patterns, w.ks, text.n)
     tuned = None
-    if args.group is None and args.sub is None and args.lane_words is None:
+    prof = valu_profile("batched")
+    explicit = not (args.group is None and args.sub is None and args.lane_words is None)
+    if not explicit and not args.autotune and prof is not None:
+        # the shape the committed counter run was taken with (chosen by the
+        # autotuner when it was made), so that its VALU count applies
+        c = prof["config"]
+        cfg = scan.BatchConfig(c["group_size"], c["sub_ranges"], c["lane_words"], 0)
+        log(f"[bench] batch shape of the committed counter run: {c}")
+    elif not explicit:
         from paper_1611_06115_amd import autotune
 
         t0 = time.perf_counter()
@@ -249,10 +276,11 @@ def run_batched(args):
     status = torch.zeros(count, dtype=torch.int32, device=dev)
     ws = torch.empty(scan.batch_workspace_bytes(text.n, batch, cfg), dtype=torch.uint8, device=dev)
     step = lambda: scan.scan_batch_async(text, batch, pos, cnt, n_hits, status, ws, config=cfg)  # noqa
-    ms = time_steps(step, args.steps, args.warmup, stream)
+    ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True)
     nh = n_hits.cpu().numpy()
     st = status.cpu().numpy()
-    log(f"[bench] {args.steps} steps, {ms:.3f} ms/step, {int(nh.sum())} hits, {int(st.sum())} incomplete")
+    log(f"[bench] {args.steps} steps, {ms:.3f} ms/step (batch kernels {kern_ms:.3f} ms), {int(nh.sum())} hits, "
+        f"{int(st.sum())} incomplete")
     # planted copies must be found
     found = {}
     for i in range(count):
@@ -265,7 +293,10 @@ def run_batched(args):
     m = batch.m.astype(np.float64)
     comps = float(((text.n - m + 1).clip(min=0) * m).sum())
     sec = ms / 1e3
-    valu = measured_valu("batched")
+    valu = None
+    if prof is not None and prof["config"] == {"group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges,
+                                               "lane_words": cfg.lane_words}:
+        valu = prof["valu_lane_ops_per_launch"]
     result = {
         "metric": "G base-pattern comparisons/sec",
         "value": round(comps / sec / 1e9, 1),
@@ -278,9 +309,12 @@ def run_batched(args):
                    "hits": int(nh.sum()), "incomplete": int(st.sum()),
                    "group_size": cfg.group_size, "sub_ranges": cfg.sub_ranges, "lane_words": cfg.lane_words,
                    "autotune": tuned},
-        "roofline": {"bound": "alu", "achieved": None if valu is None else round(valu / sec / 1e12, 2),
+        # VALU lane-ops of the batch kernels per launch (committed counter run)
+        # over their live duration
+        "roofline": {"bound": "alu",
+                     "achieved": None if valu is None else round(valu / (kern_ms / 1e3) / 1e12, 2),
                      "peak": round(VALU_PEAK_TOPS, 1), "unit": "T int32 VALU lane-ops/s",
-                     "frac": None if valu is None else round(valu / sec / 1e12 / VALU_PEAK_TOPS, 4),
+                     "frac": None if valu is None else round(valu / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4),
                      "traffic": None},
     }
     if not args.no_cpu_baseline:
@@ -454,6 +488,7 @@ def main():
     ap.add_argument("--group", type=int, default=None, help="batched: patterns per text tile")
     ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
     ap.add_argument("--lane-words", type=int, default=None, help="batched: 4 or 6")
+    ap.add_argument("--autotune", action="store_true", help="batched: tune the launch shape now")
     ap.add_argument("--n", type=int, default=None, help="override the text length")
     ap.add_argument("--qps", type=float, default=1000.0, help="served: arrival rate")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")

@@ -128,6 +128,13 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
                   void* ws_dev, uint64_t ws_bytes, void* stream);
 
+/* Measurement hook: the next pm_scan or pm_scan_batch call made by this
+ * thread records ev_begin on its stream right before its main kernel launch
+ * (the count kernel; the batched kernels) and ev_end right after it, so that
+ * a caller can time that kernel alone with hipEventElapsedTime.  Events are
+ * hipEvent_t passed as void*, created by the caller; both or neither. */
+pm_status pm_time_next_scan(void* ev_begin, void* ev_end);
+
 /* Expected number of hits of a pattern in a text of n i.i.d. uniform bases:
  * (n-m+1) times the Poisson-binomial probability that at most k of the
  * pattern's positions mismatch (per-position mismatch probability = number

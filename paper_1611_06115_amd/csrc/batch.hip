@@ -30,6 +30,8 @@ namespace pm {
 // shared with pmscan.hip
 pm_status set_error(pm_status s, const std::string& what);
 uint64_t encoded_text_groups(uint64_t n);
+hipError_t mark_begin(hipStream_t s);
+hipError_t mark_end(hipStream_t s);
 }  // namespace pm
 
 using namespace pm;
@@ -548,6 +550,7 @@ pm_status batch_run(const BatchCall& c) {
     a.span_blocks = sh.span_blocks;
     // two launches at most: the common kernel, and the deep-counter one on
     // its own queue word (queue + 1) over the remaining items
+    if ((e = mark_begin(s)) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     if (n_common > 0) {
         BatchFn fn = sh.R == 4 ? batch_kernel<4, false> : batch_kernel<6, false>;
         a.n_items = (uint32_t)n_common;
@@ -563,6 +566,7 @@ pm_status batch_run(const BatchCall& c) {
         fn<<<batch_grid(fn, w.n_items), TPB, 0, s>>>(w);
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }
+    if ((e = mark_end(s)) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     // patterns with large outputs are gathered by up to 16 workgroups each
     uint64_t max_cap = 0;
     for (uint32_t p = 0; p < count; ++p) max_cap = std::max<uint64_t>(max_cap, capacity[p]);

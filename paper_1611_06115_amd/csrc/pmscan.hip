@@ -465,6 +465,17 @@ WsLayout ws_layout(uint64_t T) {
 namespace pm {
 pm_status set_error(pm_status s, const std::string& what) { return fail(s, what); }
 uint64_t encoded_text_groups(uint64_t n) { return text_blocks(n) / 2; }
+
+// Events the next scan call of this thread records around its main kernel
+// launch(es) (pm_time_next_scan).
+thread_local hipEvent_t t_ev_begin = nullptr, t_ev_end = nullptr;
+
+hipError_t mark_begin(hipStream_t s) { return t_ev_begin ? hipEventRecord(t_ev_begin, s) : hipSuccess; }
+hipError_t mark_end(hipStream_t s) {
+    hipError_t e = t_ev_end ? hipEventRecord(t_ev_end, s) : hipSuccess;
+    t_ev_begin = t_ev_end = nullptr;
+    return e;
+}
 }  // namespace pm
 
 // ---------------------------------------------------------------------------
@@ -472,6 +483,13 @@ uint64_t encoded_text_groups(uint64_t n) { return text_blocks(n) / 2; }
 // ---------------------------------------------------------------------------
 
 extern "C" {
+
+pm_status pm_time_next_scan(void* ev_begin, void* ev_end) {
+    if ((ev_begin == nullptr) != (ev_end == nullptr)) return fail(PM_ERR_ARG, "give both events or neither");
+    pm::t_ev_begin = reinterpret_cast<hipEvent_t>(ev_begin);
+    pm::t_ev_end = reinterpret_cast<hipEvent_t>(ev_end);
+    return PM_OK;
+}
 
 const char* pm_status_string(pm_status s) {
     switch (s) {
@@ -600,8 +618,10 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     a.n_tiles = (uint32_t)n_tiles;
     a.n_chunks = (uint32_t)((n_tiles + kChunk - 1) / kChunk);
 
+    HIP_TRY(pm::mark_begin(s));
     fn.count<<<persistent_grid(fn.count, n_tiles), TPB, 0, s>>>(a, plan);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(pm::mark_end(s));
     chunk_sum_kernel<<<a.n_chunks, TPB, 0, s>>>(a);
     HIP_TRY(hipGetLastError());
     fn.place<<<(unsigned)((n_tiles + 63) / 64), TPB, 0, s>>>(a, plan);

@@ -51,6 +51,7 @@ def lib():
             "pm_scan_batch_workspace_bytes": ([u64, u32, vp, vp, vp], u64),
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
                               i32),
+            "pm_time_next_scan": ([vp, vp], i32),
             "pm_server_now_ns": ([], u64),
             "pm_server_min_arena_bytes": ([u64, vp], u64),
             "pm_server_create": ([vp, u64, vp, u64, vp, vp, vp], i32),
@@ -86,6 +87,13 @@ def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def time_next_scan(ev_begin, ev_end) -> None:
+    """Have the next scan call of this thread record two torch.cuda.Event
+    objects around its main kernel (events must have been recorded once, so
+    that they exist)."""
+    check(lib().pm_time_next_scan(ctypes.c_void_p(ev_begin.cuda_event), ctypes.c_void_p(ev_end.cuda_event)))
 
 
 # --- host-side encoding (Tables 2 and 3) -------------------------------------
