@@ -58,6 +58,20 @@ struct BatchItem {
     uint32_t first, count, sub, pad_;  // patterns [first, first+count) of the group, sub-range
 };
 
+// Pattern records and work items do not change during a launch and every
+// read of them is wave-uniform: reading them through the constant address
+// space lets those reads be scalar loads (scalar cache) instead of vector
+// loads that wait on L2.
+using CPattern = const BatchPattern __attribute__((address_space(4)));
+using CItem = const BatchItem __attribute__((address_space(4)));
+
+__device__ __forceinline__ CPattern& const_pattern(const BatchPattern* p) {
+    return *reinterpret_cast<CPattern*>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ CItem& const_item(const BatchItem* p) {
+    return *reinterpret_cast<CItem*>(reinterpret_cast<uintptr_t>(p));
+}
+
 struct GatherPattern {
     uint64_t stage_off, out_off, capacity;
     uint32_t cap_sub, pad_;
@@ -95,7 +109,7 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 // One pattern on one tile: filter, verification, and in-order append of the
 // hits to the pattern's staging area for this sub-range.
 template <int R, int L, bool EXH>
-__device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, const BatchPattern& bp, uint32_t sub,
+__device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& bp, uint32_t sub,
                                               uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
                                               uint32_t count_before) {
     TileSrc src;
@@ -137,7 +151,7 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, const Batch
 // loops: singleton filters (which need the mismatch planes) or exhaustive
 // filters (which need the raw planes).
 template <int R, bool EXH, bool WIDE>
-__device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, const BatchPattern& bp, uint32_t sub,
+__device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, CPattern& bp, uint32_t sub,
                                                 uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
                                                 uint32_t before) {
     switch (bp.variant & 7u) {
@@ -171,7 +185,7 @@ __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it
         Lane<R> s;
         make_lane<R>(txt, EXH ? 0u : 15u, s);
         for (uint32_t g = 0; g < it.count; ++g) {
-            const BatchPattern& bp = a.pats[it.first + g];
+            CPattern& bp = const_pattern(a.pats + it.first + g);
             cnt[g] += run_pattern<R, EXH, WIDE>(a, bp, it.sub, T0, wlo, whi, s, cnt[g]);
         }
     }
@@ -185,7 +199,8 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
         if (lane == 0) item = atomicAdd(a.queue, 1u);
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0, 64));
         if (item >= a.n_items) break;
-        const BatchItem it = a.items[item];
+        const BatchItem it = {const_item(a.items + item).first, const_item(a.items + item).count,
+                              const_item(a.items + item).sub, 0};
         const uint64_t blo = a.wb0 + (uint64_t)it.sub * a.span_blocks;
         const uint64_t bhi = blo + a.span_blocks;
         const uint64_t wlo = 32 * blo > a.win_begin ? 32 * blo : a.win_begin;
@@ -195,13 +210,13 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
 #pragma unroll
         for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
         if (wlo < whi) {
-            if (a.pats[it.first].variant & 8u) run_item<R, true, WIDE>(a, it, blo, wlo, whi, cnt);
+            if (const_pattern(a.pats + it.first).variant & 8u) run_item<R, true, WIDE>(a, it, blo, wlo, whi, cnt);
             else run_item<R, false, WIDE>(a, it, blo, wlo, whi, cnt);
         }
 #pragma unroll
         for (int g = 0; g < kMaxGroup; ++g)
             if ((uint32_t)g < it.count && lane == 0)
-                a.counts[(uint64_t)a.pats[it.first + g].index * a.n_sub + it.sub] = cnt[g];
+                a.counts[(uint64_t)const_pattern(a.pats + it.first + g).index * a.n_sub + it.sub] = cnt[g];
     }
 }
 

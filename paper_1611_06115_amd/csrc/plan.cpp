@@ -225,7 +225,9 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
         for (uint32_t j = 0; j < m; ++j)
             if (countable(j)) {
                 const uint32_t rel = j - 32 * ex_fw;
-                p.slot[s++] = static_cast<uint16_t>(mm[j] | ((rel >> 5) << 4) | ((rel & 31u) << 5));
+                const uint32_t v = mm[j] | ((rel >> 5) << 4) | ((rel & 31u) << 5);
+                p.slot[s / 2] |= v << (16 * (s % 2));
+                ++s;
             }
         return p;
     }
@@ -251,7 +253,7 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
         uint32_t used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         uint32_t left = J, n_sets = 0;
         auto add_set = [&](uint32_t cq, uint32_t cnt) {
-            if (2 * n_sets + 1 >= static_cast<uint32_t>(kMaxSlots)) {  // never reached: J/4 + 8 sets at most
+            if (n_sets >= static_cast<uint32_t>(kMaxSlots / 2)) {  // never reached: J/4 + 8 sets at most
                 left = 0;
                 return;
             }
@@ -259,8 +261,7 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
             for (uint32_t u = 0; u < cnt; ++u) w |= cls[cq][used[cq] + u] << (6 + 5 * u);
             used[cq] += cnt;
             left -= cnt;
-            p.slot[2 * n_sets] = static_cast<uint16_t>(w & 0xFFFFu);
-            p.slot[2 * n_sets + 1] = static_cast<uint16_t>(w >> 16);
+            p.slot[n_sets] = w;
             ++n_sets;
             p.singles |= 1u << (cq & 3u);
         };

@@ -34,13 +34,14 @@ struct ScanPlan {
     uint32_t singles;    // bit c set: the singleton plane of base c is used
     uint32_t n_sets;     // singleton filter: slot sets (32-bit words in `slot`)
     uint32_t n_groups;   // singleton filter: the first 2 * n_groups sets are full
-    // Exhaustive filter: one 16-bit slot per countable position, mm | q << 4 |
-    // r << 5 (Table 3 row, word q and shift r of its offset in the filter
-    // window).  Singleton filter: n_sets 32-bit words (low half first), each a
-    // set of up to 4 positions whose class is the same single base c and word
-    // q: c | q << 2 | count << 3 | r_u << (6 + 5u).  Pairs of full sets make
-    // the groups of 8 slots; the sets after them are the tail.
-    uint16_t slot[kMaxSlots];
+    // Exhaustive filter: one 16-bit slot per countable position, two per word
+    // (slot 2i in the low half of word i), mm | q << 4 | r << 5 (Table 3 row,
+    // word q and shift r of its offset in the filter window).  Singleton
+    // filter: n_sets words, each a set of up to 4 positions whose class is the
+    // same single base c and word q: c | q << 2 | count << 3 | r_u << (6 + 5u).
+    // Pairs of full sets make the groups of 8 slots; the sets after them are
+    // the tail.
+    uint32_t slot[kMaxSlots / 2];
 };
 
 struct PatternInfo {

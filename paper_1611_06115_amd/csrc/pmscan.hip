@@ -259,6 +259,9 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
 #pragma unroll
         for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = nxt[u];
         if (tile + nw < a.n_tiles) load_tile_text<R>(a, p, tile_first_block(a, tile + nw, R), nxt);
+        // keep those loads here, ahead of the filter (the scheduler would
+        // otherwise sink them below it, next to their use)
+        __builtin_amdgcn_sched_barrier(0);
         Counters<R, L> C;
         uint32_t hit[R], nh;
         Lane<R> s;

@@ -217,8 +217,8 @@ __device__ __forceinline__ void make_lane(const uint4 (&t)[(R + 2) / 2], uint32_
 // of lane word i (window 32*(B+i) + bit) with at most k mismatches; C keeps the
 // filter counters (the exact counts when the plan is exhaustive).  `s` holds
 // the lane's text planes starting at the plan's filter window.
-template <int R, int L, bool EXH>
-__device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& p, uint64_t B, bool interior,
+template <int R, int L, bool EXH, class Plan>
+__device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
                                             const Lane<R>& s, Counters<R, L>& C, uint32_t (&hit)[R],
                                             uint32_t& nh) {
     // ---- valid windows of each lane word ------------------------------------
@@ -247,10 +247,8 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
     // groups of 8 slots into the counters: a full-adder tree per group (pairs
     // into level 0, their carries pairwise into level 1, ...)
     if constexpr (EXH) {
-        const uint4* groups = reinterpret_cast<const uint4*>(p.slot);  // 8 slots per 16 bytes
         for (uint32_t g = 0; g < p.n_slots; g += 8) {
-            const uint4 gw = groups[g >> 3];
-            const uint32_t gv[4] = {gw.x, gw.y, gw.z, gw.w};
+            const uint32_t gv[4] = {p.slot[g / 2], p.slot[g / 2 + 1], p.slot[g / 2 + 2], p.slot[g / 2 + 3]};
             uint32_t xa[R], xb[R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
 #pragma unroll
             for (int half = 0; half < 2; ++half) {
@@ -268,15 +266,14 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
         }
     } else {
         // groups: two full sets each
-        const uint2* groups = reinterpret_cast<const uint2*>(p.slot);  // 2 sets per 8 bytes
         for (uint32_t g = 0; g < p.n_groups; ++g) {
-            const uint2 gw = groups[g];
+            const uint32_t w0 = p.slot[2 * g], w1 = p.slot[2 * g + 1];
             uint32_t X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
-            single_set<R>(gw.x, s, X);
+            single_set<R>(w0, s, X);
             add2<0, R, L>(C, X[0], X[1], c0a);
             add2<0, R, L>(C, X[2], X[3], c0b);
             add2<1, R, L>(C, c0a, c0b, c1a);
-            single_set<R>(gw.y, s, X);
+            single_set<R>(w1, s, X);
             add2<0, R, L>(C, X[0], X[1], c0a);
             add2<0, R, L>(C, X[2], X[3], c0b);
             add2<1, R, L>(C, c0a, c0b, c1b);
@@ -284,9 +281,8 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
             if constexpr (L >= 3) add1<3, R, L>(C, c2);
         }
         // tail: the remaining sets, one position at a time
-        const uint32_t* words = reinterpret_cast<const uint32_t*>(p.slot);
         for (uint32_t t = 2 * p.n_groups; t < p.n_sets; ++t) {
-            const uint32_t w = words[t];
+            const uint32_t w = p.slot[t];
             const uint32_t cnt = (w >> 3) & 7u;
             for (uint32_t u = 0; u < cnt; ++u) {
                 uint32_t X[R];
@@ -330,8 +326,8 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const ScanPlan& 
 }
 
 // Exact count of hit window `b` of lane word i.
-template <int R, int L, bool EXH>
-__device__ __forceinline__ uint32_t hit_count(const TileSrc& src, const ScanPlan& p, const Counters<R, L>& C,
+template <int R, int L, bool EXH, class Plan>
+__device__ __forceinline__ uint32_t hit_count(const TileSrc& src, const Plan& p, const Counters<R, L>& C,
                                               int i, uint32_t b, uint64_t pos) {
     if constexpr (EXH) {
         uint32_t v = 0;
