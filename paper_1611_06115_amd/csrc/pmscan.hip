@@ -320,84 +320,65 @@ __device__ __forceinline__ unsigned long long wave_sum(const T* x, uint64_t firs
     return v;
 }
 
-// Pass 3: each workgroup takes 64 consecutive tiles: one wave ranks their
-// hit counts, then every tile with hits has them placed at its ordered
-// offset -- copied from the staging area, or, for tiles with more than kCap
-// hits, found again by the whole workgroup and written directly.
+// Pass 3: each wave takes 64 consecutive tiles and ranks their hit counts;
+// every tile with hits then has them placed at its ordered offset -- copied
+// from the staging area, or, for a tile with more than kCap hits, found again
+// by the wave and written directly.  Waves of segments without hits return
+// after one load.
 template <int R, int L, bool EXH>
 __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p) {
-    __shared__ uint32_t s_count[64];
-    __shared__ unsigned long long s_prefix[64];
-    __shared__ unsigned long long s_busy;
-    const uint64_t t0 = (uint64_t)blockIdx.x * 64;
-    if (threadIdx.x < 64) {
-        const uint32_t lane = threadIdx.x;
-        if (blockIdx.x == 0) {
-            const unsigned long long all = wave_sum(a.chunk_sum, 0, a.n_chunks);
-            if (lane == 0) *a.n_hits = all;
-        }
-        const uint32_t count = t0 + lane < a.n_tiles ? a.counts[t0 + lane] : 0u;
-        const unsigned long long busy = __ballot(count != 0);
-        unsigned long long incl = count;
-        if (busy) {
-            // tiles before t0: whole chunks, then the rest of t0's chunk
-            const uint64_t c = t0 / kChunk;
-            const unsigned long long base = wave_sum(a.chunk_sum, 0, c) + wave_sum(a.counts, c * kChunk, t0);
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const unsigned long long v = __shfl_up(incl, d, 64);
-                if (lane >= (uint32_t)d) incl += v;
-            }
-            s_prefix[lane] = base + incl - count;
-        }
-        s_count[lane] = count;
-        if (lane == 0) s_busy = busy;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t seg = (uint64_t)blockIdx.x * (TPB / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t t0 = seg * 64;
+    if (seg == 0) {
+        const unsigned long long all = wave_sum(a.chunk_sum, 0, a.n_chunks);
+        if (lane == 0) *a.n_hits = all;
     }
-    __syncthreads();
-    // staged tiles: the whole workgroup copies, tile after tile
-    unsigned long long busy = s_busy;
-    unsigned long long over = 0;  // tiles to scan again (more than kCap hits)
+    if (t0 >= a.n_tiles) return;
+    const uint32_t count = t0 + lane < a.n_tiles ? a.counts[t0 + lane] : 0u;
+    unsigned long long busy = __ballot(count != 0);
+    if (busy == 0) return;
+    // hits before tile t0: whole chunks, then the rest of t0's chunk
+    const uint64_t c = t0 / kChunk;
+    const unsigned long long base = wave_sum(a.chunk_sum, 0, c) + wave_sum(a.counts, c * kChunk, t0);
+    unsigned long long incl = count;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long v = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += v;
+    }
+    const unsigned long long first = base + incl - count;  // output index of this lane's tile
     while (busy) {
         const uint32_t l = __builtin_ctzll(busy);
         busy &= busy - 1ull;
-        const uint32_t count = s_count[l];
-        const unsigned long long prefix = s_prefix[l];
-        if (prefix >= a.capacity) break;  // later tiles start even later
-        if (count > (uint32_t)kCap) {
-            over |= 1ull << l;
-            continue;
-        }
+        const uint32_t cl = __shfl(count, (int)l, 64);
+        const unsigned long long pl = __shfl(first, (int)l, 64);
+        if (pl >= a.capacity) break;  // later tiles start even later
         const uint32_t tile = (uint32_t)(t0 + l);
         const uint64_t T0 = tile_first_block(a, tile, R);
-        const unsigned long long* src = a.staged + (uint64_t)tile * kCap;
-        for (uint32_t i = threadIdx.x; i < count; i += TPB) {
-            const unsigned long long v = src[i];
-            const unsigned long long dst = prefix + i;
-            if (dst < a.capacity) {
-                a.pos[dst] = (int64_t)(32 * T0 + (v >> 16));
-                a.cnt[dst] = (uint16_t)(v & 0xFFFFu);
+        if (cl <= (uint32_t)kCap) {
+            const unsigned long long* src = a.staged + (uint64_t)tile * kCap;
+            for (uint32_t i = lane; i < cl; i += 64) {
+                const unsigned long long v = src[i];
+                const unsigned long long dst = pl + i;
+                if (dst < a.capacity) {
+                    a.pos[dst] = (int64_t)(32 * T0 + (v >> 16));
+                    a.cnt[dst] = (uint16_t)(v & 0xFFFFu);
+                }
             }
+        } else {
+            const uint64_t B = T0 + (uint64_t)lane * R;
+            uint4 txt[(R + 2) / 2];
+            load_text<R>(a, p, B, txt);
+            Counters<R, L> C;
+            uint32_t hit[R], nh;
+            Lane<R> s;
+            make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
+            tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
+            uint32_t total;
+            const uint32_t excl = wave_exclusive(nh, total);
+            if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, pl + excl);
         }
-    }
-    // tiles with more than kCap hits: wave w scans every 4th of them again
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    for (uint32_t j = 0; over; ++j) {
-        const uint32_t l = __builtin_ctzll(over);
-        over &= over - 1ull;
-        if (j % (TPB / 64) != wave) continue;
-        const uint32_t tile = (uint32_t)(t0 + l);
-        const uint64_t T0 = tile_first_block(a, tile, R);
-        const uint64_t B = T0 + (uint64_t)lane * R;
-        uint4 txt[(R + 2) / 2];
-        load_text<R>(a, p, B, txt);
-        Counters<R, L> C;
-        uint32_t hit[R], nh;
-        Lane<R> s;
-        make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-        tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
-        uint32_t total;
-        const uint32_t excl = wave_exclusive(nh, total);
-        if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, s_prefix[l] + excl);
     }
 }
 
@@ -627,7 +608,7 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     HIP_TRY(pm::mark_end(s));
     chunk_sum_kernel<<<a.n_chunks, TPB, 0, s>>>(a);
     HIP_TRY(hipGetLastError());
-    fn.place<<<(unsigned)((n_tiles + 63) / 64), TPB, 0, s>>>(a, plan);
+    fn.place<<<(unsigned)((n_tiles + 64 * (TPB / 64) - 1) / (64 * (TPB / 64))), TPB, 0, s>>>(a, plan);
     HIP_TRY(hipGetLastError());
     return PM_OK;
 }
