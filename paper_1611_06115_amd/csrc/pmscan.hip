@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 
+
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -152,7 +153,7 @@ __global__ void encode_text_kernel(const uint8_t* __restrict__ ascii, uint64_t n
 // ---------------------------------------------------------------------------
 
 constexpr int kCap = 32;      // hits a tile stages for the placement kernel
-constexpr int kChunk = 1024;  // tiles per chunk of the hit-count prefix
+constexpr uint32_t kMaxWaves = 32768;  // waves of a count-kernel grid (workspace holds one sum each)
 
 struct ScanArgs {
     TileSrc src;               // text (16-byte groups), pattern image, window range
@@ -165,9 +166,9 @@ struct ScanArgs {
     uint64_t capacity;
     unsigned long long* n_hits;
     uint32_t* counts;                // hits per tile
-    unsigned long long* chunk_sum;   // hits per chunk of kChunk tiles
+    unsigned long long* range_sum;   // hits per count-kernel wave (workgroup b's waves at 4b..4b+3)
     unsigned long long* staged;      // kCap per tile: (window offset << 16) | count
-    uint32_t n_tiles, n_chunks;
+    uint32_t n_tiles, n_waves;
 };
 
 // The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
@@ -242,23 +243,30 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 
 // Pass 1: every tile (one wave's windows) finds its hits, stores their number,
 // and stages them when there are at most kCap.  Waves are persistent and
-// independent: wave w takes tiles w, w + W, w + 2W, ... (W waves in the grid).
+// independent: each workgroup takes a contiguous range of tiles, its waves
+// take every 4th tile of it in order, and each wave stores the total hit
+// count of its tiles.
 template <int R, int L, bool EXH>
 __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t nw = gridDim.x * (TPB / 64);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
+    const uint32_t w = blockIdx.x * (TPB / 64) + wv;
+    // workgroup b takes tiles [b T / G, (b+1) T / G) of the G in the grid;
+    // its waves interleave in that range
+    constexpr uint32_t kStep = TPB / 64;
+    const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * a.n_tiles / gridDim.x);
+    uint32_t tile = (uint32_t)((uint64_t)blockIdx.x * a.n_tiles / gridDim.x) + wv;
+    uint32_t sum = 0;
     // the text of the wave's next tile is loaded while this one is computed
     uint4 nxt[(R + 2) / 2];
-    uint32_t tile = blockIdx.x * (TPB / 64) + wave;
-    if (tile < a.n_tiles) load_tile_text<R>(a, p, tile_first_block(a, tile, R), nxt);
-    for (; tile < a.n_tiles; tile += nw) {
+    if (tile < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile, R), nxt);
+    for (; tile < t_end; tile += kStep) {
         const uint64_t T0 = tile_first_block(a, tile, R);
         const uint64_t B = T0 + (uint64_t)lane * R;
         uint4 txt[(R + 2) / 2];
 #pragma unroll
         for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = nxt[u];
-        if (tile + nw < a.n_tiles) load_tile_text<R>(a, p, tile_first_block(a, tile + nw, R), nxt);
+        if (tile + kStep < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile + kStep, R), nxt);
         // keep those loads here, ahead of the filter (the scheduler would
         // otherwise sink them below it, next to their use)
         __builtin_amdgcn_sched_barrier(0);
@@ -274,6 +282,7 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
         uint32_t total;
         const uint32_t excl = wave_exclusive(nh, total);
         if (lane == 0) a.counts[tile] = total;
+        sum += total;
         if (total > (uint32_t)kCap || nh == 0) continue;
         unsigned long long* out = a.staged + (uint64_t)tile * kCap + excl;
         const uint64_t base = 32 * T0;
@@ -289,24 +298,7 @@ __global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p)
             }
         }
     }
-}
-
-// Pass 2: hits per chunk of kChunk tiles.
-__global__ __launch_bounds__(TPB) void chunk_sum_kernel(ScanArgs a) {
-    const uint64_t first = (uint64_t)blockIdx.x * kChunk;
-    unsigned long long v = 0;
-    for (uint32_t t = threadIdx.x; t < (uint32_t)kChunk; t += TPB)
-        if (first + t < a.n_tiles) v += a.counts[first + t];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    __shared__ unsigned long long s[TPB / 64];
-    if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < TPB / 64; ++w) t += s[w];
-        a.chunk_sum[blockIdx.x] = t;
-    }
+    if (lane == 0) a.range_sum[w] = sum;
 }
 
 // Wave sum of x[first .. last) (all 64 lanes of one wave call it).
@@ -331,16 +323,21 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
     const uint64_t seg = (uint64_t)blockIdx.x * (TPB / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t0 = seg * 64;
     if (seg == 0) {
-        const unsigned long long all = wave_sum(a.chunk_sum, 0, a.n_chunks);
+        const unsigned long long all = wave_sum(a.range_sum, 0, a.n_waves);
         if (lane == 0) *a.n_hits = all;
     }
     if (t0 >= a.n_tiles) return;
     const uint32_t count = t0 + lane < a.n_tiles ? a.counts[t0 + lane] : 0u;
     unsigned long long busy = __ballot(count != 0);
     if (busy == 0) return;
-    // hits before tile t0: whole chunks, then the rest of t0's chunk
-    const uint64_t c = t0 / kChunk;
-    const unsigned long long base = wave_sum(a.chunk_sum, 0, c) + wave_sum(a.counts, c * kChunk, t0);
+    // hits before tile t0: the ranges of the count kernel's workgroups before
+    // the one that owns t0 (the last whose range starts at or before t0), then
+    // that range's tiles before t0
+    const uint32_t G = a.n_waves / (TPB / 64);
+    uint32_t b0 = (uint32_t)(t0 * G / a.n_tiles);
+    while (b0 + 1 < G && (uint64_t)(b0 + 1) * a.n_tiles / G <= t0) ++b0;
+    const uint64_t s0 = (uint64_t)b0 * a.n_tiles / G;
+    const unsigned long long base = wave_sum(a.range_sum, 0, (uint64_t)b0 * (TPB / 64)) + wave_sum(a.counts, s0, t0);
     unsigned long long incl = count;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -417,7 +414,7 @@ unsigned persistent_grid(ScanFn fn, uint64_t n_tiles) {
         cus = 256;
         per_cu = 2;
     }
-    return (unsigned)std::min<uint64_t>(n_tiles, (uint64_t)cus * (uint64_t)per_cu);
+    return (unsigned)std::min<uint64_t>({n_tiles, (uint64_t)cus * (uint64_t)per_cu, kMaxWaves / (TPB / 64)});
 }
 
 uint64_t text_blocks(uint64_t n) { return ((n + 31) / 32 + kPadBlocks + 1) & ~1ull; }
@@ -430,16 +427,16 @@ uint64_t max_tiles(uint64_t n) {
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
-// Workspace layout for up to T tiles: hit counts (u32 per tile), chunk sums
-// (u64 per kChunk tiles), staged hits (kCap u64 per tile).
+// Workspace layout for up to T tiles: hit counts (u32 per tile), hit sums
+// (u64 per count-kernel wave), staged hits (kCap u64 per tile).
 struct WsLayout {
-    uint64_t counts, chunk_sum, staged, bytes;
+    uint64_t counts, range_sum, staged, bytes;
 };
 WsLayout ws_layout(uint64_t T) {
     WsLayout w;
     w.counts = 0;
-    w.chunk_sum = align256(4 * T);
-    w.staged = w.chunk_sum + align256(8 * ((T + kChunk - 1) / kChunk));
+    w.range_sum = align256(4 * T);
+    w.staged = w.range_sum + align256(8ull * kMaxWaves);
     w.bytes = w.staged + 8 * (uint64_t)kCap * T;
     return w;
 }
@@ -597,17 +594,16 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     a.capacity = capacity;
     a.n_hits = reinterpret_cast<unsigned long long*>(n_hits_dev);
     a.counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
-    a.chunk_sum = reinterpret_cast<unsigned long long*>(ws + lay.chunk_sum);
+    a.range_sum = reinterpret_cast<unsigned long long*>(ws + lay.range_sum);
     a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
     a.n_tiles = (uint32_t)n_tiles;
-    a.n_chunks = (uint32_t)((n_tiles + kChunk - 1) / kChunk);
+    const unsigned grid = persistent_grid(fn.count, n_tiles);
+    a.n_waves = grid * (TPB / 64);
 
     HIP_TRY(pm::mark_begin(s));
-    fn.count<<<persistent_grid(fn.count, n_tiles), TPB, 0, s>>>(a, plan);
+    fn.count<<<grid, TPB, 0, s>>>(a, plan);
     HIP_TRY(hipGetLastError());
     HIP_TRY(pm::mark_end(s));
-    chunk_sum_kernel<<<a.n_chunks, TPB, 0, s>>>(a);
-    HIP_TRY(hipGetLastError());
     fn.place<<<(unsigned)((n_tiles + 64 * (TPB / 64) - 1) / (64 * (TPB / 64))), TPB, 0, s>>>(a, plan);
     HIP_TRY(hipGetLastError());
     return PM_OK;
