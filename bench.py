@@ -74,32 +74,35 @@ def valu_profile(workload: str):
 def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
     """Mean ms per step over `steps` timed steps (HIP events on `stream`).
     With kernel=True also the mean duration of the scan's main kernel, from
-    a pair of events the library records around that launch in every step."""
+    a pair of events the library records around that launch; those events
+    go into a second timed loop of the same steps, so that they do not
+    perturb the step time."""
     import torch
 
     from paper_1611_06115_amd import scan
 
     for _ in range(warmup):
         fn()
-    pairs = []
-    if kernel:
-        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-        for a, b in pairs:  # creates the events
-            a.record(stream)
-            b.record(stream)
     stream.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for i in range(steps):
-        if kernel:
-            scan.time_next_scan(*pairs[i])
+    for _ in range(steps):
         fn()
     e1.record(stream)
     e1.synchronize()
     step_ms = e0.elapsed_time(e1) / steps
     if not kernel:
         return step_ms
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in pairs:  # creates the events
+        a.record(stream)
+        b.record(stream)
+    stream.synchronize()
+    for i in range(steps):
+        scan.time_next_scan(*pairs[i])
+        fn()
+    stream.synchronize()
     return step_ms, sum(a.elapsed_time(b) for a, b in pairs) / steps
 
 

@@ -173,7 +173,7 @@ __device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, CPattern& bp
 
 template <int R, bool EXH, bool WIDE>
 __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it, uint64_t blo, uint64_t wlo,
-                                         uint64_t whi, uint32_t (&cnt)[kMaxGroup]) {
+                                         uint64_t whi, uint32_t* cnt) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t tile = 64ull * R;
     for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
@@ -186,7 +186,9 @@ __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it
         make_lane<R>(txt, EXH ? 0u : 15u, s);
         for (uint32_t g = 0; g < it.count; ++g) {
             CPattern& bp = const_pattern(a.pats + it.first + g);
-            cnt[g] += run_pattern<R, EXH, WIDE>(a, bp, it.sub, T0, wlo, whi, s, cnt[g]);
+            const uint32_t before = __builtin_amdgcn_readfirstlane(cnt[g]);
+            const uint32_t added = run_pattern<R, EXH, WIDE>(a, bp, it.sub, T0, wlo, whi, s, before);
+            if ((threadIdx.x & 63u) == 0) cnt[g] = before + added;
         }
     }
 }
@@ -205,18 +207,18 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
         const uint64_t bhi = blo + a.span_blocks;
         const uint64_t wlo = 32 * blo > a.win_begin ? 32 * blo : a.win_begin;
         const uint64_t whi = 32 * bhi < a.win_end ? 32 * bhi : a.win_end;
-        // per-pattern running hit counts of this item (wave-uniform)
-        uint32_t cnt[kMaxGroup];
-#pragma unroll
-        for (int g = 0; g < kMaxGroup; ++g) cnt[g] = 0;
+        // per-pattern running hit counts of this item, in the wave's LDS slice
+        // (indexed by the pattern's place in the group, which is not a
+        // compile-time constant, so registers would be addressed indirectly)
+        __shared__ uint32_t s_cnt[TPB / 64][kMaxGroup];
+        uint32_t* cnt = s_cnt[threadIdx.x >> 6];
+        if (lane < (uint32_t)kMaxGroup) cnt[lane] = 0;
         if (wlo < whi) {
             if (const_pattern(a.pats + it.first).variant & 8u) run_item<R, true, WIDE>(a, it, blo, wlo, whi, cnt);
             else run_item<R, false, WIDE>(a, it, blo, wlo, whi, cnt);
         }
-#pragma unroll
-        for (int g = 0; g < kMaxGroup; ++g)
-            if ((uint32_t)g < it.count && lane == 0)
-                a.counts[(uint64_t)const_pattern(a.pats + it.first + g).index * a.n_sub + it.sub] = cnt[g];
+        if (lane < it.count)
+            a.counts[(uint64_t)const_pattern(a.pats + it.first + lane).index * a.n_sub + it.sub] = cnt[lane];
     }
 }
 

@@ -246,8 +246,12 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 // independent: each workgroup takes a contiguous range of tiles, its waves
 // take every 4th tile of it in order, and each wave stores the total hit
 // count of its tiles.
+// Up to 3 counter levels the kernel is held to 5 waves per SIMD (a few
+// registers spill; measured faster than 4 waves); deeper counters keep the
+// compiler's choice.
 template <int R, int L, bool EXH>
-__global__ __launch_bounds__(TPB) void scan_count_kernel(ScanArgs a, ScanPlan p) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 5 : 1)))
+void scan_count_kernel(ScanArgs a, ScanPlan p) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
     const uint32_t w = blockIdx.x * (TPB / 64) + wv;
