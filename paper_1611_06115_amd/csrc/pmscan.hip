@@ -153,7 +153,7 @@ __global__ void encode_text_kernel(const uint8_t* __restrict__ ascii, uint64_t n
 // ---------------------------------------------------------------------------
 
 constexpr int kCap = 32;      // hits a tile stages for the placement kernel
-constexpr uint32_t kMaxWaves = 32768;  // waves of a count-kernel grid (workspace holds one sum each)
+constexpr uint32_t kMaxRanges = 16384;  // workgroups of a count-kernel grid (workspace holds one sum each)
 
 struct ScanArgs {
     TileSrc src;               // text (16-byte groups), pattern image, window range
@@ -166,9 +166,9 @@ struct ScanArgs {
     uint64_t capacity;
     unsigned long long* n_hits;
     uint32_t* counts;                // hits per tile
-    unsigned long long* range_sum;   // hits per count-kernel wave (workgroup b's waves at 4b..4b+3)
+    unsigned long long* range_sum;   // hits per count-kernel workgroup (its range of tiles)
     unsigned long long* staged;      // kCap per tile: (window offset << 16) | count
-    uint32_t n_tiles, n_waves;
+    uint32_t n_tiles, n_ranges;
 };
 
 // The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
@@ -244,8 +244,8 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 // Pass 1: every tile (one wave's windows) finds its hits, stores their number,
 // and stages them when there are at most kCap.  Waves are persistent and
 // independent: each workgroup takes a contiguous range of tiles, its waves
-// take every 4th tile of it in order, and each wave stores the total hit
-// count of its tiles.
+// take every 4th tile of it in order, and the workgroup stores the total hit
+// count of its range.
 // Up to 3 counter levels the kernel is held to 5 waves per SIMD (a few
 // registers spill; measured faster than 4 waves); deeper counters keep the
 // compiler's choice.
@@ -254,7 +254,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 5 
 void scan_count_kernel(ScanArgs a, ScanPlan p) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
-    const uint32_t w = blockIdx.x * (TPB / 64) + wv;
     // workgroup b takes tiles [b T / G, (b+1) T / G) of the G in the grid;
     // its waves interleave in that range
     constexpr uint32_t kStep = TPB / 64;
@@ -302,15 +301,33 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
             }
         }
     }
-    if (lane == 0) a.range_sum[w] = sum;
+    // the workgroup's total: one sum per range
+    __shared__ uint32_t s_sum[TPB / 64];
+    if (lane == 0) s_sum[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+#pragma unroll
+        for (int i = 0; i < TPB / 64; ++i) t += s_sum[i];
+        a.range_sum[blockIdx.x] = t;
+    }
 }
 
 // Wave sum of x[first .. last) (all 64 lanes of one wave call it).
 template <typename T>
 __device__ __forceinline__ unsigned long long wave_sum(const T* x, uint64_t first, uint64_t last) {
     const uint32_t lane = threadIdx.x & 63u;
-    unsigned long long v = 0;
-    for (uint64_t i = first + lane; i < last; i += 64) v += x[i];
+    // four loads per lane in flight at a time
+    unsigned long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
+    uint64_t i = first + lane;
+    for (; i + 192 < last; i += 256) {
+        v0 += x[i];
+        v1 += x[i + 64];
+        v2 += x[i + 128];
+        v3 += x[i + 192];
+    }
+    for (; i < last; i += 64) v0 += x[i];
+    unsigned long long v = (v0 + v1) + (v2 + v3);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
     const uint64_t seg = (uint64_t)blockIdx.x * (TPB / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t t0 = seg * 64;
     if (seg == 0) {
-        const unsigned long long all = wave_sum(a.range_sum, 0, a.n_waves);
+        const unsigned long long all = wave_sum(a.range_sum, 0, a.n_ranges);
         if (lane == 0) *a.n_hits = all;
     }
     if (t0 >= a.n_tiles) return;
@@ -337,11 +354,11 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
     // hits before tile t0: the ranges of the count kernel's workgroups before
     // the one that owns t0 (the last whose range starts at or before t0), then
     // that range's tiles before t0
-    const uint32_t G = a.n_waves / (TPB / 64);
+    const uint32_t G = a.n_ranges;
     uint32_t b0 = (uint32_t)(t0 * G / a.n_tiles);
     while (b0 + 1 < G && (uint64_t)(b0 + 1) * a.n_tiles / G <= t0) ++b0;
     const uint64_t s0 = (uint64_t)b0 * a.n_tiles / G;
-    const unsigned long long base = wave_sum(a.range_sum, 0, (uint64_t)b0 * (TPB / 64)) + wave_sum(a.counts, s0, t0);
+    const unsigned long long base = wave_sum(a.range_sum, 0, b0) + wave_sum(a.counts, s0, t0);
     unsigned long long incl = count;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -418,7 +435,7 @@ unsigned persistent_grid(ScanFn fn, uint64_t n_tiles) {
         cus = 256;
         per_cu = 2;
     }
-    return (unsigned)std::min<uint64_t>({n_tiles, (uint64_t)cus * (uint64_t)per_cu, kMaxWaves / (TPB / 64)});
+    return (unsigned)std::min<uint64_t>({n_tiles, (uint64_t)cus * (uint64_t)per_cu, kMaxRanges});
 }
 
 uint64_t text_blocks(uint64_t n) { return ((n + 31) / 32 + kPadBlocks + 1) & ~1ull; }
@@ -432,7 +449,7 @@ uint64_t max_tiles(uint64_t n) {
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Workspace layout for up to T tiles: hit counts (u32 per tile), hit sums
-// (u64 per count-kernel wave), staged hits (kCap u64 per tile).
+// (u64 per count-kernel workgroup), staged hits (kCap u64 per tile).
 struct WsLayout {
     uint64_t counts, range_sum, staged, bytes;
 };
@@ -440,7 +457,7 @@ WsLayout ws_layout(uint64_t T) {
     WsLayout w;
     w.counts = 0;
     w.range_sum = align256(4 * T);
-    w.staged = w.range_sum + align256(8ull * kMaxWaves);
+    w.staged = w.range_sum + align256(8ull * kMaxRanges);
     w.bytes = w.staged + 8 * (uint64_t)kCap * T;
     return w;
 }
@@ -602,7 +619,7 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
     a.n_tiles = (uint32_t)n_tiles;
     const unsigned grid = persistent_grid(fn.count, n_tiles);
-    a.n_waves = grid * (TPB / 64);
+    a.n_ranges = grid;
 
     HIP_TRY(pm::mark_begin(s));
     fn.count<<<grid, TPB, 0, s>>>(a, plan);
