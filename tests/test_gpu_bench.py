@@ -1,0 +1,82 @@
+"""The benchmark's output contract on the GPU (small sizes), and the
+kernel-timing hook it relies on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+from conftest import ROOT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def run_bench(*args, timeout=240):
+    out = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), *args], cwd=ROOT,
+                         capture_output=True, text=True, timeout=timeout)
+    assert out.returncode == 0, out.stderr[-2000:]
+    lines = [l for l in out.stdout.splitlines() if l.startswith("{")]
+    assert len(lines) == 1, out.stdout
+    return json.loads(lines[0])
+
+
+def check_contract(r):
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline"):
+        assert key in r, key
+    assert r["n_gpus"] == 1 and r["value"] > 0 and r["ms_per_step"] > 0
+    assert "workload" in r["config"]
+    rl = r["roofline"]
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in rl, key
+    assert rl["bound"] in ("hbm", "mfma", "alu")
+
+
+def test_bench_plain_contract():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "small", "--steps", "3", "--warmup", "1")
+    check_contract(r)
+    assert r["roofline"]["bound"] == "hbm" and 0 < r["roofline"]["frac"] < 1.5
+    cb = r["cpu_baseline"]
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
+
+
+def test_bench_served_contract():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "served", "--n", "30000000", "--count", "500", "--qps", "200", "--duration", "1",
+                  "--arena-gib", "4", "--no-cpu-baseline")
+    check_contract(r)
+    lat = r["latency_ms"]
+    assert 0 < lat["p50"] <= lat["p99"] <= lat["max"]
+    assert r["config"]["queries"] > 50
+
+
+def test_time_next_scan_brackets_the_count_kernel():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1611_06115_amd import scan, synth
+
+    w = synth.small(n=2_000_000)
+    t = scan.encode_text(w.text)
+    pat = scan.Pattern(w.patterns[0])
+    ws = scan.Workspace(t.data.device, t.n, 1 << 16)
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    b.record(s)
+    e0.record(s)
+    scan.time_next_scan(a, b)
+    scan.scan_async(t, pat, 2, ws)
+    e1.record(s)
+    e1.synchronize()
+    k_ms, step_ms = a.elapsed_time(b), e0.elapsed_time(e1)
+    assert 0 < k_ms <= step_ms
+    import ctypes
+
+    with pytest.raises(scan.PMError):  # both events or neither
+        scan.check(scan.lib().pm_time_next_scan(None, ctypes.c_void_p(b.cuda_event)))

@@ -88,3 +88,13 @@ def test_min_arena_grows_with_text_and_chunks():
 def test_server_clock_is_monotonic():
     t = [server.now_ns() for _ in range(100)]
     assert all(x <= y for x, y in zip(t, t[1:])) and t[0] > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stdout
