@@ -32,6 +32,7 @@ pm_status set_error(pm_status s, const std::string& what);
 uint64_t encoded_text_groups(uint64_t n);
 hipError_t mark_begin(hipStream_t s);
 hipError_t mark_end(hipStream_t s);
+uint64_t resident_blocks(const void* fn);
 }  // namespace pm
 
 using namespace pm;
@@ -366,17 +367,7 @@ pm_status check_batch_args(uint32_t count, const uint32_t* m, const uint32_t* k,
 using BatchFn = void (*)(BatchArgs);
 
 unsigned batch_grid(BatchFn fn, uint64_t items) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), TPB, 0) !=
-            hipSuccess ||
-        cus <= 0 || per_cu <= 0) {
-        cus = 256;
-        per_cu = 2;
-    }
-    const uint64_t waves_needed = items;
-    const uint64_t blocks = std::min<uint64_t>((uint64_t)cus * per_cu, (waves_needed + 3) / 4);
+    const uint64_t blocks = std::min<uint64_t>(resident_blocks(reinterpret_cast<const void*>(fn)), (items + 3) / 4);
     return (unsigned)std::max<uint64_t>(blocks, 1);
 }
 

@@ -30,12 +30,18 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/pmscan.h"
 #include "plan.hpp"
 #include "scan_core.hpp"
+
+namespace pm {
+uint64_t resident_blocks(const void* fn);
+}  // namespace pm
 
 using pm::ScanPlan;
 using namespace pm;
@@ -426,16 +432,8 @@ ScanPair pick_scan(const ScanPlan& p) {
 // Workgroups for a persistent kernel: as many as fit on the device at once
 // (occupancy per CU x CUs), never more than there are tiles.
 unsigned persistent_grid(ScanFn fn, uint64_t n_tiles) {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), TPB, 0) !=
-            hipSuccess ||
-        cus <= 0 || per_cu <= 0) {
-        cus = 256;
-        per_cu = 2;
-    }
-    return (unsigned)std::min<uint64_t>({n_tiles, (uint64_t)cus * (uint64_t)per_cu, kMaxRanges});
+    const uint64_t resident = pm::resident_blocks(reinterpret_cast<const void*>(fn));
+    return (unsigned)std::min<uint64_t>({n_tiles, resident, kMaxRanges});
 }
 
 uint64_t text_blocks(uint64_t n) { return ((n + 31) / 32 + kPadBlocks + 1) & ~1ull; }
@@ -466,6 +464,30 @@ WsLayout ws_layout(uint64_t T) {
 
 namespace pm {
 pm_status set_error(pm_status s, const std::string& what) { return fail(s, what); }
+
+// Workgroups of `fn` (TPB threads) that fit on the current device at once,
+// queried once per (device, kernel).
+uint64_t resident_blocks(const void* fn) {
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, uint64_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find({dev, fn});
+        if (it != cache.end()) return it->second;
+    }
+    int cus = 0, per_cu = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, TPB, 0) != hipSuccess || cus <= 0 || per_cu <= 0) {
+        cus = 256;
+        per_cu = 2;
+    }
+    const uint64_t r = (uint64_t)cus * (uint64_t)per_cu;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[{dev, fn}] = r;
+    return r;
+}
 uint64_t encoded_text_groups(uint64_t n) { return text_blocks(n) / 2; }
 
 // Events the next scan call of this thread records around its main kernel
