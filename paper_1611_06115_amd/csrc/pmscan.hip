@@ -252,11 +252,11 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 // independent: each workgroup takes a contiguous range of tiles, its waves
 // take every 4th tile of it in order, and the workgroup stores the total hit
 // count of its range.
-// Up to 3 counter levels the kernel is held to 5 waves per SIMD (a few
-// registers spill; measured faster than 4 waves); deeper counters keep the
-// compiler's choice.
+// With 4 lane words and up to 3 counter levels the kernel is held to 5 waves
+// per SIMD (its registers fit; measured faster than 4 waves); other shapes
+// keep the compiler's choice.
 template <int R, int L, bool EXH>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(L <= 3 ? 5 : 1)))
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(R == 4 && L <= 3 ? 5 : 1)))
 void scan_count_kernel(ScanArgs a, ScanPlan p) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
