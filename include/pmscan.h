@@ -148,7 +148,8 @@ pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_
 
 typedef struct {
     uint32_t group_size;  /* patterns sharing each text tile (1..16); 0 = 8          */
-    uint32_t sub_ranges;  /* text sub-ranges per pattern group (1..1000); 0 = auto   */
+    uint32_t sub_ranges;  /* text sub-ranges per pattern group (1..4096); 0 = auto:  */
+                          /* about 32768 work items per call                          */
     uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = 4                 */
     uint32_t reserved;
 } pm_batch_config;
@@ -203,7 +204,10 @@ typedef struct {
     uint32_t chunks;          /* window ranges per revolution of the text; 0 = 8      */
     uint32_t max_active;      /* queries scanned together (slots); 0 = 1024           */
     uint64_t workspace_bytes; /* arena bytes kept for the batch workspace; 0 = 1/4   */
-    pm_batch_config batch;    /* shape of the batched launches; zeros = defaults      */
+    pm_batch_config batch;    /* shape of the batched launches; zeros = defaults.     */
+                              /* sub_ranges 0: admission sizes the workspace for 64   */
+                              /* per group, each step takes up to the automatic count */
+                              /* for its queries as far as the workspace allows       */
 } pm_server_config;
 
 #define PM_QUERY_WAITING 0    /* submitted, not admitted yet           */

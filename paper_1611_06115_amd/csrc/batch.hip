@@ -231,31 +231,49 @@ __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* 
                                                            uint32_t n_sub, const unsigned long long* staged,
                                                            int64_t* pos, uint16_t* cnt,
                                                            unsigned long long* n_hits, uint32_t* status) {
-    __shared__ unsigned long long s_off[1024 + 1];
+    __shared__ unsigned long long s_off[kMaxSubRanges + 1];
+    __shared__ unsigned long long s_part[TPB];
     __shared__ uint32_t s_flag;
     const uint32_t p = blockIdx.x;
     const GatherPattern g = gp[p];
-    for (uint32_t s = threadIdx.x; s < n_sub; s += TPB) s_off[s + 1] = counts[(uint64_t)p * n_sub + s];
-    __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long run = 0;
-        uint32_t over = 0;
+        s_flag = 0;
         s_off[0] = 0;
-        for (uint32_t s = 0; s < n_sub; ++s) {
-            const unsigned long long c = s_off[s + 1];
-            if (c > g.cap_sub) over = 1;
-            run += c;
-            s_off[s + 1] = run;
-        }
-        if (run > g.capacity) over = 1;
-        if (blockIdx.y == 0) {
-            n_hits[p] = run;
-            status[p] = over;
-        }
-        s_flag = over;
     }
+    // each thread sums a contiguous run of sub-ranges, the runs' totals are
+    // scanned across the workgroup, and each thread then forms its offsets
+    const uint32_t per = (n_sub + TPB - 1) / TPB;
+    const uint32_t s0 = min(n_sub, threadIdx.x * per), s1 = min(n_sub, s0 + per);
+    unsigned long long run = 0;
+    bool over = false;
+    for (uint32_t s = s0; s < s1; ++s) {
+        const uint32_t c = counts[(uint64_t)p * n_sub + s];
+        over |= c > g.cap_sub;
+        s_off[s + 1] = c;
+        run += c;
+    }
+    s_part[threadIdx.x] = run;
     __syncthreads();
-    if (s_flag) return;
+    for (uint32_t d = 1; d < TPB; d <<= 1) {
+        const unsigned long long v = threadIdx.x >= d ? s_part[threadIdx.x - d] : 0;
+        __syncthreads();
+        s_part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    unsigned long long base = threadIdx.x ? s_part[threadIdx.x - 1] : 0;
+    for (uint32_t s = s0; s < s1; ++s) {
+        base += s_off[s + 1];
+        s_off[s + 1] = base;
+    }
+    const unsigned long long total = s_part[TPB - 1];
+    if (over) atomicOr(&s_flag, 1u);
+    __syncthreads();
+    const uint32_t bad = (s_flag || total > g.capacity) ? 1u : 0u;
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+        n_hits[p] = total;
+        status[p] = bad;
+    }
+    if (bad) return;
     for (uint32_t s = blockIdx.y; s < n_sub; s += gridDim.y) {
         const uint64_t first = s_off[s];
         const uint32_t c = (uint32_t)(s_off[s + 1] - first);
@@ -299,14 +317,8 @@ BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, u
     BatchShape sh;
     sh.G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 8;
     sh.R = cfg && cfg->lane_words == 6 ? 6 : 4;
-    const uint64_t groups = (count + sh.G - 1) / sh.G;
-    uint32_t S = cfg && cfg->sub_ranges ? cfg->sub_ranges : 0;
-    if (S == 0) {
-        // about 8 items per wave that fits on the device (~16 per CU)
-        const uint64_t want = 8ull * 256 * 16;
-        S = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(256, (want + groups - 1) / std::max<uint64_t>(groups, 1)));
-    }
-    S = std::min<uint32_t>(S, 1000);
+    uint32_t S = cfg && cfg->sub_ranges ? cfg->sub_ranges : batch_auto_sub_ranges(count, cfg);
+    S = std::min<uint32_t>(S, kMaxSubRanges);
     sh.S = S;
     if (win_end > n) win_end = n;
     if (win_begin > win_end) win_begin = win_end;
@@ -374,6 +386,12 @@ unsigned batch_grid(BatchFn fn, uint64_t items) {
 }  // namespace
 
 namespace pm {
+
+uint32_t batch_auto_sub_ranges(uint32_t count, const pm_batch_config* cfg) {
+    const uint64_t G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 8;
+    const uint64_t groups = std::max<uint64_t>(1, (count + G - 1) / G);
+    return (uint32_t)std::min<uint64_t>(kMaxSubRanges, (kAutoItems + groups - 1) / groups);
+}
 
 uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
                         const pm_batch_config* cfg, bool with_images) {

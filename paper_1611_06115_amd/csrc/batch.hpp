@@ -46,6 +46,16 @@ struct BatchCall {
 
 pm_status batch_run(const BatchCall& c);
 
+// Text sub-ranges per pattern group: at most kMaxSubRanges.  The automatic
+// choice aims at about kAutoItems work items per launch (eight per wave that
+// fits on the device), so that a call with few patterns still fills the chip.
+constexpr uint32_t kMaxSubRanges = 4096;
+constexpr uint64_t kAutoItems = 8ull * 256 * 16;
+
+// The sub-range count a call over `count` patterns takes when
+// cfg->sub_ranges is 0.
+uint32_t batch_auto_sub_ranges(uint32_t count, const pm_batch_config* cfg);
+
 // Workspace bytes of a call over these patterns; with_images = false when
 // the caller keeps the images on the device.
 uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,

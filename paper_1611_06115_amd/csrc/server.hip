@@ -62,6 +62,7 @@ constexpr uint64_t kImageStage = 1ull << 20;
 constexpr uint32_t kJoinSlots = 4;
 constexpr uint64_t kBigJoin = 1ull << 20;  // results this large are joined out of place
 constexpr uint64_t kPiece = 1ull << 18;    // hit slots per join workgroup out of place
+constexpr uint32_t kAdmitSubRanges = 64;  // sub-ranges per group that admission sizes the workspace for
 
 uint64_t clock_ns() {
     return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
@@ -225,7 +226,14 @@ struct pm_server {
     uint64_t n = 0;
     uint32_t C = 8, max_active = 1024;
     uint64_t W = 0;  // windows per chunk
+    // Admission sizes the workspace with bcfg.  When the caller left the
+    // sub-range count to the library, bcfg holds the floor kAdmitSubRanges
+    // and each step takes the most sub-ranges (up to the automatic choice
+    // for its query count) that fit the workspace: the floor always fits,
+    // since a step set is a subset of an admitted set and the workspace at a
+    // fixed sub-range count only grows with the set.
     pm_batch_config bcfg{};
+    bool adaptive_sub = false;
     hipStream_t main = nullptr, aux = nullptr;
     hipEvent_t step_ev[2] = {nullptr, nullptr};
     uint8_t* ws = nullptr;
@@ -390,7 +398,17 @@ struct pm_server {
             ms[i] = q->m;
             caps[i] = q->cap;
         }
-        const uint64_t need = batch_desc_bytes(n, count, ms.data(), caps.data(), &bcfg, false);
+        pm_batch_config scfg = bcfg;
+        if (adaptive_sub) {
+            uint32_t S = std::max(kAdmitSubRanges, batch_auto_sub_ranges(count, &bcfg));
+            for (;;) {
+                scfg.sub_ranges = S;
+                if (S <= kAdmitSubRanges || batch_ws_bytes(n, count, ms.data(), caps.data(), &scfg, false) <= ws_bytes)
+                    break;
+                S = std::max(kAdmitSubRanges, S / 2);
+            }
+        }
+        const uint64_t need = batch_desc_bytes(n, count, ms.data(), caps.data(), &scfg, false);
         if (!desc[slot].grow(need) || !host_nh[slot].grow(8ull * count) || !host_st[slot].grow(4ull * count)) {
             fail_engine(PM_ERR_HIP, "hipHostMalloc failed");
             return false;
@@ -409,7 +427,7 @@ struct pm_server {
         c.status_dev = dev_st[slot];
         c.ws_dev = ws;
         c.ws_bytes = ws_bytes;
-        c.cfg = &bcfg;
+        c.cfg = &scfg;
         c.desc_host = static_cast<uint8_t*>(desc[slot].p);
         c.desc_host_bytes = desc[slot].bytes;
         c.stream = main;
@@ -785,16 +803,17 @@ ArenaPlan plan_arena(uint64_t n, uint64_t arena_bytes, uint32_t C, uint32_t max_
 }
 
 void normalise(const pm_server_config* cfg, uint64_t arena_bytes, uint32_t& C, uint32_t& max_active,
-               uint64_t& ws_bytes, pm_batch_config& b) {
+               uint64_t& ws_bytes, pm_batch_config& b, bool* adaptive = nullptr) {
     C = cfg && cfg->chunks ? cfg->chunks : 8;
     max_active = cfg && cfg->max_active ? cfg->max_active : 1024;
     ws_bytes = cfg && cfg->workspace_bytes ? cfg->workspace_bytes : align256(arena_bytes / 4);
     std::memset(&b, 0, sizeof(b));
     if (cfg) b = cfg->batch;
-    // A fixed number of sub-ranges keeps the batch workspace a sum of
-    // per-query terms, so a step set that loses queries never needs more
-    // workspace than the set that was admitted.
-    if (b.sub_ranges == 0) b.sub_ranges = 256;
+    // Admission works at a fixed sub-range count, which keeps the batch
+    // workspace monotone in the query set; steps may take more (see
+    // pm_server::adaptive_sub).
+    if (adaptive) *adaptive = b.sub_ranges == 0;
+    if (b.sub_ranges == 0) b.sub_ranges = kAdmitSubRanges;
 }
 
 }  // namespace
@@ -822,7 +841,8 @@ pm_status pm_server_create(const void* text_dev, uint64_t n, void* arena_dev, ui
     uint32_t C, max_active;
     uint64_t ws_bytes;
     pm_batch_config b;
-    normalise(cfg, arena_bytes, C, max_active, ws_bytes, b);
+    bool adaptive = false;
+    normalise(cfg, arena_bytes, C, max_active, ws_bytes, b, &adaptive);
     if (C > 4096) return set_error(PM_ERR_ARG, "chunks above 4096");
     if (max_active > (1u << 20)) return set_error(PM_ERR_ARG, "max_active above 2^20");
     const ArenaPlan a = plan_arena(n, arena_bytes, C, max_active, ws_bytes);
@@ -837,6 +857,7 @@ pm_status pm_server_create(const void* text_dev, uint64_t n, void* arena_dev, ui
     s->max_active = max_active;
     s->W = (n + C - 1) / C;
     s->bcfg = b;
+    s->adaptive_sub = adaptive;
     s->main = reinterpret_cast<hipStream_t>(stream);
     uint8_t* base = static_cast<uint8_t*>(arena_dev);
     s->ws = base + a.ws;

@@ -59,6 +59,46 @@ def test_batch_matches_oracle(pm, group, sub, lane_words):
     check_batch(pm, t, text, pats, ks, res, f"g{group} s{sub}")
 
 
+@pytest.mark.parametrize("group,sub,lane_words", [(8, 0, 4), (1, 4096, 6)])
+def test_batch_many_sub_ranges(pm, group, sub, lane_words):
+    """A few patterns over a 40e6-base text: the automatic choice (and an
+    explicit 4096) cuts every group into 4096 sub-ranges, which the gather
+    step's offset scan concatenates; lists equal the plain kernel's, and
+    every planted copy is found."""
+    from paper_1611_06115_amd import synth
+
+    rnd = random.Random(4096 + group)
+    text = synth.iid_text(40_000_000, seed=synth.SEED0 + 80 + group)
+    no_gap = "ACGTMRWSYKVHDBN"  # every position of these patterns has a base that matches it
+    pats = [rand_pattern(rnd, 24, 0.1, no_gap), "GATTACAGATTACA", rand_pattern(rnd, 200, 0.2, no_gap), "ACGTNNACGT"]
+    ks = [1, 2, 12, 0]
+    from oracle import reference as ref
+
+    # exact copies (a base of each position's class), one per disjoint
+    # 250 kb slot so that no copy overwrites another
+    planted = []
+    slot = len(text) // (40 * len(pats))
+    for i, p in enumerate(pats):
+        sets = ref.parse(p)
+        for c in range(40):
+            p0 = (i * 40 + c) * slot + rnd.randrange(0, slot - len(sets))
+            for j, s in enumerate(sets):
+                text[p0 + j] = ord(rnd.choice(sorted(s)))
+            planted.append((i, p0))
+    t = pm.encode_text(text)
+    cfg = pm.BatchConfig(group, sub, lane_words, 0)
+    say(f"batch many sub-ranges group={group} sub={sub} R={lane_words} n={t.n}")
+    res = pm.scan_batch(t, pats, ks, config=cfg, rerun=False)
+    for i, (p, k) in enumerate(zip(pats, ks)):
+        assert res[i] is not None, f"pattern {i} overflowed its staging"
+        got = (res[i][0].cpu().numpy(), res[i][1].cpu().numpy())
+        plain = pm.scan(t, pm.Pattern(p), k)
+        assert_same(got, (plain[0].cpu().numpy(), plain[1].cpu().numpy()), f"sub-ranges pattern {i}")
+    found = {(i, int(x)) for i, r in enumerate(res) for x in r[0].cpu().numpy().tolist()}
+    for i, p0 in planted:
+        assert (i, p0) in found
+
+
 def test_batch_deep_counters_and_edge_patterns(pm):
     """k up to 60 (5 and 6 counter levels, the second kernel), no-filter
     patterns (k >= 64), patterns longer than the text, all N / all '-'."""

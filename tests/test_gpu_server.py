@@ -94,7 +94,7 @@ def test_served_under_memory_pressure(pm, served_text):
     # the server's per-chunk capacity of each query, and the workspace and
     # hit slots of the largest one: the arena holds about two of those
     caps = [-(-(int(2 * scan.expected_hits(scan.Pattern(pats[i]), ks[i], t.n)) + 64 * C) // C) for i in sub]
-    bc = scan.BatchConfig(0, 256, 0, 0)
+    bc = scan.BatchConfig(0, 64, 0, 0)  # the sub-range count admission sizes for
     ws_one = max(scan.batch_workspace_bytes(t.n, scan.Batch([pats[i]], [ks[i]], t.n, capacities=[c]), bc)
                  for i, c in zip(sub, caps))
     cfg = server.ServerConfig(chunks=C, max_active=3, workspace_bytes=(2 * ws_one + 255) // 256 * 256)
