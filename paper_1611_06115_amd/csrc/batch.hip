@@ -223,10 +223,14 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
     }
 }
 
-// Workgroups (p, y): concatenate pattern p's sub-ranges in text order, y
-// taking the sub-ranges s = y, y + gridDim.y, ...  Every workgroup of p forms
-// the same offsets from the per-sub-range counts; (p, 0) reports the total
-// and the status.
+// Workgroups (p, y): concatenate pattern p's sub-ranges in text order.
+// Every workgroup of p forms the sub-ranges' output offsets from their hit
+// counts (a workgroup-wide scan in LDS); workgroup y then writes its share of
+// p's outputs, each thread finding the sub-range of an output slot by binary
+// search over the offsets, with kGatherVec loads in flight.  (p, 0) reports
+// the total and the status.
+constexpr int kGatherVec = 8;
+
 __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* gp, const uint32_t* counts,
                                                            uint32_t n_sub, const unsigned long long* staged,
                                                            int64_t* pos, uint16_t* cnt,
@@ -236,10 +240,13 @@ __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* 
     __shared__ uint32_t s_flag;
     const uint32_t p = blockIdx.x;
     const GatherPattern g = gp[p];
+    const uint32_t* cp = counts + (uint64_t)p * n_sub;
     if (threadIdx.x == 0) {
         s_flag = 0;
         s_off[0] = 0;
     }
+    for (uint32_t s = threadIdx.x; s < n_sub; s += TPB) s_off[s + 1] = cp[s];
+    __syncthreads();
     // each thread sums a contiguous run of sub-ranges, the runs' totals are
     // scanned across the workgroup, and each thread then forms its offsets
     const uint32_t per = (n_sub + TPB - 1) / TPB;
@@ -247,9 +254,8 @@ __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* 
     unsigned long long run = 0;
     bool over = false;
     for (uint32_t s = s0; s < s1; ++s) {
-        const uint32_t c = counts[(uint64_t)p * n_sub + s];
+        const unsigned long long c = s_off[s + 1];
         over |= c > g.cap_sub;
-        s_off[s + 1] = c;
         run += c;
     }
     s_part[threadIdx.x] = run;
@@ -274,14 +280,36 @@ __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* 
         status[p] = bad;
     }
     if (bad) return;
-    for (uint32_t s = blockIdx.y; s < n_sub; s += gridDim.y) {
-        const uint64_t first = s_off[s];
-        const uint32_t c = (uint32_t)(s_off[s + 1] - first);
-        const unsigned long long* src = staged + g.stage_off + (uint64_t)s * g.cap_sub;
-        for (uint32_t i = threadIdx.x; i < c; i += TPB) {
-            const unsigned long long v = src[i];
-            pos[g.out_off + first + i] = (int64_t)(v >> 16);
-            cnt[g.out_off + first + i] = (uint16_t)(v & 0xFFFFu);
+    const unsigned long long share = (total + gridDim.y - 1) / gridDim.y;
+    const unsigned long long lo = min(total, (unsigned long long)blockIdx.y * share);
+    const unsigned long long hi = min(total, lo + share);
+    const unsigned long long* src = staged + g.stage_off;
+    int64_t* po = pos + g.out_off;
+    uint16_t* co = cnt + g.out_off;
+    for (unsigned long long i0 = lo; i0 < hi; i0 += (unsigned long long)TPB * kGatherVec) {
+        unsigned long long v[kGatherVec];
+#pragma unroll
+        for (int j = 0; j < kGatherVec; ++j) {
+            const unsigned long long i = i0 + (unsigned long long)j * TPB + threadIdx.x;
+            v[j] = 0;
+            if (i < hi) {
+                // s_off[a] <= i < s_off[b]; s_off[0] = 0 and s_off[n_sub] = total > i
+                uint32_t a = 0, b = n_sub;
+                while (b - a > 1) {
+                    const uint32_t mid = (a + b) >> 1;
+                    if (s_off[mid] <= i) a = mid;
+                    else b = mid;
+                }
+                v[j] = src[(uint64_t)a * g.cap_sub + (i - s_off[a])];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kGatherVec; ++j) {
+            const unsigned long long i = i0 + (unsigned long long)j * TPB + threadIdx.x;
+            if (i < hi) {
+                po[i] = (int64_t)(v[j] >> 16);
+                co[i] = (uint16_t)(v[j] & 0xFFFFu);
+            }
         }
     }
 }
@@ -593,10 +621,12 @@ pm_status batch_run(const BatchCall& c) {
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }
     if ((e = mark_end(s)) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
-    // patterns with large outputs are gathered by up to 16 workgroups each
+    // one gather workgroup per 64K output slots of the largest pattern, up to
+    // 1024 per pattern and about 64K workgroups in all
     uint64_t max_cap = 0;
     for (uint32_t p = 0; p < count; ++p) max_cap = std::max<uint64_t>(max_cap, capacity[p]);
-    const uint32_t gy = (uint32_t)std::min<uint64_t>({16, sh.S, std::max<uint64_t>(1, max_cap >> 16)});
+    const uint64_t gy_cap = std::max<uint64_t>(1, std::min<uint64_t>(1024, 65536 / count));
+    const uint32_t gy = (uint32_t)std::min<uint64_t>(gy_cap, std::max<uint64_t>(1, (max_cap + 65535) >> 16));
     batch_gather_kernel<<<dim3(count, gy), TPB, 0, s>>>(reinterpret_cast<const GatherPattern*>(ws + L.gather),
                                                         a.counts, sh.S, a.staged, c.pos_dev, c.cnt_dev,
                                                         reinterpret_cast<unsigned long long*>(c.n_hits_dev),
