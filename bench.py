@@ -36,9 +36,17 @@ def log(*a):
 VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # int32 VALU lane-ops/s: CUs x lanes per clock x clock
 
 
-def kernel_source_sha() -> str:
+# The sources that define each workload's kernels: a committed counter run
+# applies only while these are unchanged.
+KERNEL_SOURCES = {
+    "genome": ("pmscan.hip", "plan.cpp", "plan.hpp", "scan_core.hpp"),
+    "batched": ("batch.hip", "batch.hpp", "plan.cpp", "plan.hpp", "scan_core.hpp"),
+}
+
+
+def kernel_source_sha(workload: str = "genome") -> str:
     h = hashlib.sha256()
-    for f in ("pmscan.hip", "plan.cpp", "plan.hpp", "scan_core.hpp", "batch.hip", "batch.hpp"):
+    for f in KERNEL_SOURCES[workload]:
         with open(os.path.join(ROOT, "paper_1611_06115_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -52,7 +60,7 @@ def measured_traffic(workload: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha(workload):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -66,7 +74,7 @@ def valu_profile(workload: str):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_sha():
+    if t.get("kernel_source_sha") != kernel_source_sha(workload):
         return None
     return t
 
