@@ -179,3 +179,44 @@ def test_batched_workload_sample(pm):
     found = {(i, int(p)) for i, r in enumerate(res) for p in r[0].cpu().tolist()}
     for pi, p, d in w.plants:
         assert (pi, p) in found
+
+
+def test_batched_workload_full(pm):
+    """The batched workload at full size (256e6 bases, 4096 patterns) in the
+    launch shape of the committed counter run the benchmark times (group 8,
+    64 sub-ranges, 4 lane words) and in the automatic shape: every planted
+    copy is found, 48 seeded patterns' lists equal the plain kernel's, and
+    on a seeded window range of each the oracle's."""
+    from paper_1611_06115_amd import synth
+
+    w = synth.batched()
+    say(f"batched full: n={w.n} patterns={len(w.patterns)}")
+    ascii_dev = torch.from_numpy(w.text).cuda()
+    t = pm.encode_text(ascii_dev)
+    torch.cuda.synchronize()
+    t.check()
+    del ascii_dev
+    torch.cuda.empty_cache()
+    batch = pm.Batch(w.patterns, w.ks, t.n)
+    rnd = random.Random(48)
+    sample = sorted(rnd.sample(range(len(w.patterns)), 48))
+    ranges = {i: rnd.randrange(0, t.n - len(w.patterns[i]) + 1 - 500_000) for i in sample}
+    plants = {}
+    for pi, p, d in w.plants:
+        plants.setdefault(pi, []).append(p)
+    for cfg in (pm.BatchConfig(8, 64, 4, 0), pm.BatchConfig(0, 0, 0, 0)):
+        say(f"  shape group={cfg.group_size} sub={cfg.sub_ranges} R={cfg.lane_words}")
+        res = pm.scan_batch(t, batch, None, config=cfg)
+        for pi, ps in plants.items():
+            got = res[pi][0].cpu().numpy()
+            assert np.isin(np.array(ps, dtype=np.int64), got).all(), f"pattern {pi} plants {ps}"
+        for i in sample:
+            pat, k = w.patterns[i], w.ks[i]
+            got = (res[i][0].cpu().numpy(), res[i][1].cpu().numpy())
+            plain = pm.scan(t, pm.Pattern(pat), k)
+            assert_same(got, (plain[0].cpu().numpy(), plain[1].cpu().numpy()), f"full batch pattern {i} vs plain")
+            b = ranges[i]
+            want = oracle_hits(w.text, pat, k, win_begin=b, win_end=b + 500_000)
+            sel = (got[0] >= b) & (got[0] < b + 500_000)
+            assert_same((got[0][sel], got[1][sel]), want, f"full batch pattern {i} range {b} vs oracle")
+        say(f"  {len(sample)} sampled patterns equal to the plain kernel and the oracle")

@@ -195,3 +195,58 @@ def test_served_large_results(pm):
     assert res[0][0].size == t.n - 11
     for i, (p, k) in enumerate(zip(pats, ks)):
         assert_same(res[i], alone(scan, t, p, k), f"large query {i}")
+
+
+def test_served_genome_scale(pm):
+    """The served workload at full size: the 3.1e9-base genome resident, the
+    engine configured as the benchmark runs it (8 chunks, 1024 slots, 64 GiB
+    arena), 240 seeded pool queries submitted in bursts while earlier ones
+    are on the GPU.  Every result equals the plain kernel run alone (compared
+    on the device), every planted copy is found, and for queries with few
+    hits sampled hit counts and a seeded window range equal the oracle's."""
+    import oracle
+
+    scan, server = pm
+    from paper_1611_06115_amd import synth
+
+    w = synth.served()
+    say(f"served genome scale: n={w.n}, pool {len(w.patterns)}")
+    ascii_dev = torch.from_numpy(w.text).cuda()
+    t = scan.encode_text(ascii_dev)
+    torch.cuda.synchronize()
+    t.check()
+    del ascii_dev
+    torch.cuda.empty_cache()
+    rnd = random.Random(240)
+    qs = sorted(rnd.sample(range(len(w.patterns)), 240))
+    plant = {i: p for i, p, d in w.plants}
+    with server.Server(t, 64 << 30, server.ServerConfig()) as srv:
+        ids = []
+        for j, i in enumerate(qs):
+            ids.append(srv.submit(w.patterns[i], w.ks[i]))
+            if j % 40 == 39:
+                time.sleep(0.005)
+        checked = 0
+        for qid, i in zip(ids, qs):
+            pat, k = w.patterns[i], w.ks[i]
+            pos, cnt = srv.result(qid, timeout_ms=120_000)
+            ppos, pcnt = scan.scan(t, scan.Pattern(pat), k)
+            assert torch.equal(pos, ppos) and torch.equal(cnt, pcnt), f"query {i} m={len(pat)} k={k} vs plain"
+            at = int(torch.searchsorted(pos, torch.tensor([plant[i]], device=pos.device)).item())
+            assert at < pos.numel() and int(pos[at].item()) == plant[i], f"query {i} plant {plant[i]}"
+            if pos.numel() < 200_000 and checked < 16:
+                hp, hc = pos.cpu().numpy(), cnt.cpu().numpy()
+                sets = oracle.parse(pat)
+                for jj in rnd.sample(range(hp.size), min(hp.size, 100)):
+                    p0 = int(hp[jj])
+                    assert oracle.counts(w.text[p0:p0 + len(pat)], sets).tolist() == [int(hc[jj])]
+                b = rnd.randrange(0, w.n - len(pat) + 1 - 200_000)
+                want = oracle_hits(w.text, pat, k, win_begin=b, win_end=b + 200_000)
+                sel = (hp >= b) & (hp < b + 200_000)
+                assert_same((hp[sel], hc[sel]), want, f"query {i} range {b} vs oracle")
+                checked += 1
+            del pos, cnt, ppos, pcnt
+        st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] >= len(qs) and st["failed"] == 0
+    assert checked == 16
