@@ -542,12 +542,14 @@ pm_status batch_run(const BatchCall& c) {
             th.emplace_back(prepare, (uint32_t)((uint64_t)count * t / nt), (uint32_t)((uint64_t)count * (t + 1) / nt));
         for (auto& x : th) x.join();
     }
-    // groups: same variant, similar cost; items: (group, sub-range), costly first
+    // groups: same variant, similar filter cost, then similar length (the
+    // cost of verifying a survivor); items: (group, sub-range), costly first
     std::vector<uint32_t> order(count);
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
         if (pats[x].variant != pats[y].variant) return pats[x].variant < pats[y].variant;
-        return cost[x] > cost[y];
+        if (cost[x] != cost[y]) return cost[x] > cost[y];
+        return pats[x].plan.nchunks > pats[y].plan.nchunks;
     });
     for (uint32_t i = 0; i < count; ++i) sorted[i] = pats[order[i]];
     struct Group {
