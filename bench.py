@@ -149,6 +149,7 @@ def run_plain(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
+    pi = 0  # which of the workload's patterns is scanned
     if args.workload == "genome":
         w = synth.genome(n=args.n or 3_100_000_000)
         pattern, k = w.patterns[0], w.ks[0]
@@ -192,7 +193,7 @@ def run_plain(args):
     pos = ws.pos[:min(hits, ws.capacity)].cpu().numpy()
     cnt = ws.cnt[:min(hits, ws.capacity)].cpu().numpy()
     found = dict(zip(pos.tolist(), cnt.tolist()))
-    missed = [(p, d) for _, p, d in w.plants if d <= k and found.get(p) != d]
+    missed = [(p, d) for q, p, d in w.plants if q == pi and d <= k and found.get(p) != d]
     if missed:
         raise SystemExit(f"planted sites missed or miscounted: {missed[:5]}")
 

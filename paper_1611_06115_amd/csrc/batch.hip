@@ -78,6 +78,11 @@ struct GatherPattern {
     uint32_t cap_sub, pad_;
 };
 
+// One gather workgroup: share y of the nb shares of pattern p's output.
+struct GatherWork {
+    uint32_t p, y, nb, pad_;
+};
+
 struct BatchArgs {
     const uint4* text4;
     uint32_t n4_last;               // last 16-byte group of the text buffer
@@ -223,29 +228,45 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
     }
 }
 
-// Workgroups (p, y): concatenate pattern p's sub-ranges in text order.
-// Every workgroup of p forms the sub-ranges' output offsets from their hit
-// counts (a workgroup-wide scan in LDS); workgroup y then writes its share of
-// p's outputs, each thread finding the sub-range of an output slot by binary
-// search over the offsets, with kGatherVec loads in flight.  (p, 0) reports
-// the total and the status.
+// One workgroup per work entry (p, y, nb): concatenate pattern p's
+// sub-ranges in text order.  Every workgroup of p forms the sub-ranges'
+// output offsets from their hit counts (a workgroup-wide scan in LDS); it
+// then writes share y of nb of p's outputs, each thread finding the
+// sub-range of an output slot by binary search over the offsets, with
+// kGatherVec loads in flight.  Share 0 reports the total and the status.
 constexpr int kGatherVec = 8;
 
-__global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* gp, const uint32_t* counts,
-                                                           uint32_t n_sub, const unsigned long long* staged,
-                                                           int64_t* pos, uint16_t* cnt,
-                                                           unsigned long long* n_hits, uint32_t* status) {
-    __shared__ unsigned long long s_off[kMaxSubRanges + 1];
+__global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* gp, const GatherWork* work,
+                                                           const uint32_t* counts, uint32_t n_sub,
+                                                           const unsigned long long* staged, int64_t* pos,
+                                                           uint16_t* cnt, unsigned long long* n_hits,
+                                                           uint32_t* status) {
+    extern __shared__ unsigned long long s_off[];  // n_sub + 1 entries (dynamic)
     __shared__ unsigned long long s_part[TPB];
     __shared__ uint32_t s_flag;
-    const uint32_t p = blockIdx.x;
+    const GatherWork wk = work[blockIdx.x];
+    const uint32_t p = wk.p;
     const GatherPattern g = gp[p];
     const uint32_t* cp = counts + (uint64_t)p * n_sub;
     if (threadIdx.x == 0) {
         s_flag = 0;
         s_off[0] = 0;
     }
-    for (uint32_t s = threadIdx.x; s < n_sub; s += TPB) s_off[s + 1] = cp[s];
+    // the counts (up to 16 per thread) are loaded together, then stored
+    constexpr uint32_t kCountVec = (kMaxSubRanges + TPB - 1) / TPB;
+    for (uint32_t s0 = threadIdx.x; s0 < n_sub; s0 += TPB * kCountVec) {
+        uint32_t c[kCountVec];
+#pragma unroll
+        for (uint32_t j = 0; j < kCountVec; ++j) {
+            const uint32_t s = s0 + j * TPB;
+            c[j] = s < n_sub ? cp[s] : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kCountVec; ++j) {
+            const uint32_t s = s0 + j * TPB;
+            if (s < n_sub) s_off[s + 1] = c[j];
+        }
+    }
     __syncthreads();
     // each thread sums a contiguous run of sub-ranges, the runs' totals are
     // scanned across the workgroup, and each thread then forms its offsets
@@ -275,13 +296,13 @@ __global__ __launch_bounds__(TPB) void batch_gather_kernel(const GatherPattern* 
     if (over) atomicOr(&s_flag, 1u);
     __syncthreads();
     const uint32_t bad = (s_flag || total > g.capacity) ? 1u : 0u;
-    if (blockIdx.y == 0 && threadIdx.x == 0) {
+    if (wk.y == 0 && threadIdx.x == 0) {
         n_hits[p] = total;
         status[p] = bad;
     }
     if (bad) return;
-    const unsigned long long share = (total + gridDim.y - 1) / gridDim.y;
-    const unsigned long long lo = min(total, (unsigned long long)blockIdx.y * share);
+    const unsigned long long share = (total + wk.nb - 1) / wk.nb;
+    const unsigned long long lo = min(total, (unsigned long long)wk.y * share);
     const unsigned long long hi = min(total, lo + share);
     const unsigned long long* src = staged + g.stage_off;
     int64_t* po = pos + g.out_off;
@@ -333,8 +354,16 @@ struct BatchShape {
 // Workspace layout.  The descriptor (patterns, gather records, images, work
 // items) comes first and is copied from the host in one piece up to the last
 // item in use; the queue words and the counts are zeroed on the device.
+// Gather workgroups of a pattern: one per 64K output slots, at most 1024,
+// and at most 65536 / count so that a call launches about 64K in all.
+uint32_t gather_blocks(uint64_t capacity, uint32_t count) {
+    const uint64_t cap = std::max<uint64_t>(1, std::min<uint64_t>(1024, 65536 / std::max<uint32_t>(count, 1)));
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, (capacity + 65535) >> 16));
+}
+
 struct BatchLayout {
-    uint64_t pats, gather, images, items, queue, counts, staged, bytes;
+    uint64_t pats, gather, gwork, images, items, queue, counts, staged, bytes;
+    uint64_t n_gwork;
     std::vector<uint64_t> image_off, stage_off;
     std::vector<uint32_t> cap_sub;
     uint64_t n_items_max;
@@ -380,6 +409,10 @@ BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capa
     off = align256(off + sizeof(BatchPattern) * (uint64_t)count);
     L.gather = off;
     off = align256(off + sizeof(GatherPattern) * (uint64_t)count);
+    L.n_gwork = 0;
+    for (uint32_t p = 0; p < count; ++p) L.n_gwork += gather_blocks(capacity[p], count);
+    L.gwork = off;
+    off = align256(off + sizeof(GatherWork) * L.n_gwork);
     L.images = off;
     off = align256(off + 16 * img);
     L.items = off;
@@ -492,6 +525,14 @@ pm_status batch_run(const BatchCall& c) {
     }
     BatchPattern* sorted = reinterpret_cast<BatchPattern*>(desc + L.pats);
     GatherPattern* gat = reinterpret_cast<GatherPattern*>(desc + L.gather);
+    GatherWork* gwork = reinterpret_cast<GatherWork*>(desc + L.gwork);
+    {
+        uint64_t e = 0;
+        for (uint32_t p = 0; p < count; ++p) {
+            const uint32_t nb = gather_blocks(capacity[p], count);
+            for (uint32_t y = 0; y < nb; ++y) gwork[e++] = {p, y, nb, 0u};
+        }
+    }
     uint32_t* img_words = reinterpret_cast<uint32_t*>(desc + L.images);
     BatchItem* items = reinterpret_cast<BatchItem*>(desc + L.items);
 
@@ -623,16 +664,10 @@ pm_status batch_run(const BatchCall& c) {
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }
     if ((e = mark_end(s)) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
-    // one gather workgroup per 64K output slots of the largest pattern, up to
-    // 1024 per pattern and about 64K workgroups in all
-    uint64_t max_cap = 0;
-    for (uint32_t p = 0; p < count; ++p) max_cap = std::max<uint64_t>(max_cap, capacity[p]);
-    const uint64_t gy_cap = std::max<uint64_t>(1, std::min<uint64_t>(1024, 65536 / count));
-    const uint32_t gy = (uint32_t)std::min<uint64_t>(gy_cap, std::max<uint64_t>(1, (max_cap + 65535) >> 16));
-    batch_gather_kernel<<<dim3(count, gy), TPB, 0, s>>>(reinterpret_cast<const GatherPattern*>(ws + L.gather),
-                                                        a.counts, sh.S, a.staged, c.pos_dev, c.cnt_dev,
-                                                        reinterpret_cast<unsigned long long*>(c.n_hits_dev),
-                                                        c.status_dev);
+    batch_gather_kernel<<<(unsigned)L.n_gwork, TPB, 8 * (sh.S + 1), s>>>(
+        reinterpret_cast<const GatherPattern*>(ws + L.gather), reinterpret_cast<const GatherWork*>(ws + L.gwork),
+        a.counts, sh.S, a.staged, c.pos_dev, c.cnt_dev, reinterpret_cast<unsigned long long*>(c.n_hits_dev),
+        c.status_dev);
     if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     return PM_OK;
 }

@@ -168,22 +168,39 @@ __device__ __forceinline__ void add1(Counters<R, L>& c, uint32_t (&a)[R]) {
 }
 
 // Exact count of one window, all m positions (pattern image), stopping once
-// the count exceeds `limit`.
+// the count exceeds `limit` (then the value returned is only known to exceed
+// it).  Chunks of 32 positions are taken four at a time, their loads issued
+// together, so a long pattern's count waits on a quarter of the load round
+// trips.
 __device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* __restrict__ image,
                                  uint32_t nchunks, uint64_t s, uint32_t limit) {
     const uint2* text = reinterpret_cast<const uint2*>(text4);
     const uint64_t q = s >> 5;
     const uint32_t r = (uint32_t)s & 31u;
+    constexpr uint32_t V = 4;
     uint2 w0 = text[q];
     uint32_t cnt = 0;
-    for (uint32_t c = 0; c < nchunks; ++c) {
-        const uint2 w1 = text[q + c + 1];
-        const uint32_t H = align(w1.x, w0.x, r), Lo = align(w1.y, w0.y, r);
-        const uint4 mp = image[c];
-        const uint32_t mis = (~H & ~Lo & mp.x) | (~H & Lo & mp.y) | (H & ~Lo & mp.z) | (H & Lo & mp.w);
-        cnt += __builtin_popcount(mis);
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += V) {
+        uint2 w[V];
+        uint4 mp[V];
+#pragma unroll
+        for (uint32_t j = 0; j < V; ++j) {
+            if (c0 + j < nchunks) {
+                w[j] = text[q + c0 + j + 1];
+                mp[j] = image[c0 + j];
+            } else {
+                w[j] = w0;
+                mp[j] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < V; ++j) {
+            const uint32_t H = align(w[j].x, w0.x, r), Lo = align(w[j].y, w0.y, r);
+            const uint32_t mis = (~H & ~Lo & mp[j].x) | (~H & Lo & mp[j].y) | (H & ~Lo & mp[j].z) | (H & Lo & mp[j].w);
+            cnt += __builtin_popcount(mis);
+            w0 = w[j];
+        }
         if (cnt > limit) break;
-        w0 = w1;
     }
     return cnt;
 }
