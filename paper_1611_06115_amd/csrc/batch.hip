@@ -129,7 +129,7 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& b
     const bool interior = 32 * T0 >= src.win_begin && 32 * (T0 + 64ull * R) <= src.win_end;
     Counters<R, L> C;
     uint32_t hit[R], nh;
-    tile_filter<R, L, EXH>(src, bp.plan, B, interior, s, C, hit, nh);
+    tile_filter<R, L, EXH, false>(src, bp.plan, B, interior, s, C, hit, nh);
     if (__ballot(nh != 0) == 0) return 0;
     uint32_t total;
     uint32_t idx = count_before + wave_exclusive(nh, total);

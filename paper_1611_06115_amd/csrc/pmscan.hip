@@ -283,7 +283,7 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
         uint32_t hit[R], nh;
         Lane<R> s;
         make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-        tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
+        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
         if (__ballot(nh != 0) == 0) {  // the usual case: no hits in the tile
             if (lane == 0) a.counts[tile] = 0;
             continue;
@@ -292,9 +292,43 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
         const uint32_t excl = wave_exclusive(nh, total);
         if (lane == 0) a.counts[tile] = total;
         sum += total;
-        if (total > (uint32_t)kCap || nh == 0) continue;
-        unsigned long long* out = a.staged + (uint64_t)tile * kCap + excl;
+        if (total > (uint32_t)kCap) continue;
         const uint64_t base = 32 * T0;
+        if (!EXH && p.nchunks > kWaveVerifyChunks) {
+            // long patterns: the hits in position order (the staging order),
+            // each counted by the whole wave and written by its lane
+            unsigned long long* out = a.staged + (uint64_t)tile * kCap;
+            for (uint32_t j = 0;; ++j) {
+                uint32_t mine = 0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) mine |= hit[i];
+                const uint64_t bal = __ballot(mine != 0);
+                if (bal == 0) break;
+                const uint32_t owner = (uint32_t)__builtin_ctzll(bal);
+                int fi = 0;
+                uint32_t fb = 0;
+#pragma unroll
+                for (int i = R - 1; i >= 0; --i)
+                    if (hit[i]) {
+                        fi = i;
+                        fb = __builtin_ctz(hit[i]);
+                    }
+                const uint64_t mine_pos = 32 * (B + (uint64_t)fi) + fb;
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine_pos, owner);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine_pos >> 32), owner);
+                const uint64_t pos = ((uint64_t)hi << 32) | lo;
+                const uint32_t c = count_window_wave(a.src.text4, a.src.image, p.nchunks, pos, p.k, lane);
+                if (lane == owner) {
+                    out[j] = ((pos - base) << 16) | c;
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (i == fi) hit[i] &= hit[i] - 1u;
+                }
+            }
+            continue;
+        }
+        if (nh == 0) continue;
+        unsigned long long* out = a.staged + (uint64_t)tile * kCap + excl;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
             uint32_t h = hit[i];
@@ -398,7 +432,7 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
             uint32_t hit[R], nh;
             Lane<R> s;
             make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-            tile_filter<R, L, EXH>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
+            tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
             uint32_t total;
             const uint32_t excl = wave_exclusive(nh, total);
             if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, pl + excl);

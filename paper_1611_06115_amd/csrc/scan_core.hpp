@@ -205,6 +205,54 @@ __device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* _
     return cnt;
 }
 
+// Exact count of window s by the whole wave (every lane active): lane l
+// takes the chunks of 32 positions l, l + 64, ..., one per round; the wave's
+// sum is tested against `limit` after each round.  Returns the same value in every lane (exact when <= limit).
+__device__ uint32_t count_window_wave(const uint4* __restrict__ text4, const uint4* __restrict__ image,
+                                      uint32_t nchunks, uint64_t s, uint32_t limit, uint32_t lane) {
+    const uint2* text = reinterpret_cast<const uint2*>(text4);
+    const uint64_t q = s >> 5;
+    const uint32_t r = (uint32_t)s & 31u;
+    constexpr uint32_t V = 1;
+    uint32_t total = 0;
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += 64 * V) {
+        uint2 w0[V], w1[V];
+        uint4 mp[V];
+#pragma unroll
+        for (uint32_t j = 0; j < V; ++j) {
+            const uint32_t c = c0 + 64 * j + lane;
+            if (c < nchunks) {
+                w0[j] = text[q + c];
+                w1[j] = text[q + c + 1];
+                mp[j] = image[c];
+            } else {
+                w0[j] = make_uint2(0u, 0u);
+                w1[j] = w0[j];
+                mp[j] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+        uint32_t part = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < V; ++j) {
+            const uint32_t H = align(w1[j].x, w0[j].x, r), Lo = align(w1[j].y, w0[j].y, r);
+            const uint32_t mis = (~H & ~Lo & mp[j].x) | (~H & Lo & mp[j].y) | (H & ~Lo & mp[j].z) | (H & Lo & mp[j].w);
+            part += __builtin_popcount(mis);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+        total += part;
+        if (total > limit) break;
+    }
+    return total;
+}
+
+// With WV, survivors of patterns longer than kWaveVerifyChunks chunks of 32
+// positions are verified by the whole wave, one at a time, when at most
+// kWaveVerifyLanes lanes have any (the usual case with a selective filter);
+// otherwise each lane verifies its own survivors.
+constexpr uint32_t kWaveVerifyChunks = 16;
+constexpr int kWaveVerifyLanes = 4;
+
 // The lane's text planes for blocks B+fw .. B+fw+R+1 (the 16-byte groups in
 // t) and, for each base c with bit c of `singles` set, its mismatch plane:
 // bit set where the text base is not c.
@@ -234,7 +282,7 @@ __device__ __forceinline__ void make_lane(const uint4 (&t)[(R + 2) / 2], uint32_
 // of lane word i (window 32*(B+i) + bit) with at most k mismatches; C keeps the
 // filter counters (the exact counts when the plan is exhaustive).  `s` holds
 // the lane's text planes starting at the plan's filter window.
-template <int R, int L, bool EXH, class Plan>
+template <int R, int L, bool EXH, bool WV, class Plan>
 __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
                                             const Lane<R>& s, Counters<R, L>& C, uint32_t (&hit)[R],
                                             uint32_t& nh) {
@@ -324,6 +372,46 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, u
         if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
 #pragma unroll
             for (int i = 0; i < R; ++i) hit[i] = 0;
+            return;
+        }
+        if (WV && p.nchunks > kWaveVerifyChunks && __popcll(__ballot(any != 0)) <= kWaveVerifyLanes) {
+            // survivors in position order (lowest lane first, then its words
+            // and bits), each counted by the whole wave; a verified survivor
+            // is marked dead, a hit set in hit[]
+            const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+            for (int i = 0; i < R; ++i) hit[i] = 0;
+            for (;;) {
+                uint32_t mine = 0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) mine |= ~C.dead[i];
+                const uint64_t bal = __ballot(mine != 0);
+                if (bal == 0) break;
+                const uint32_t owner = (uint32_t)__builtin_ctzll(bal);
+                int fi = 0;
+                uint32_t fb = 0;
+#pragma unroll
+                for (int i = R - 1; i >= 0; --i)
+                    if (~C.dead[i]) {
+                        fi = i;
+                        fb = __builtin_ctz(~C.dead[i]);
+                    }
+                const uint64_t mine_pos = 32 * (B + (uint64_t)fi) + fb;
+                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine_pos, owner);
+                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine_pos >> 32), owner);
+                const uint64_t pos = ((uint64_t)hi << 32) | lo;
+                const uint32_t c = count_window_wave(src.text4, src.image, p.nchunks, pos, p.k, lane);
+                if (lane == owner) {
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (i == fi) {
+                            C.dead[i] |= 1u << fb;
+                            if (c <= p.k) hit[i] |= 1u << fb;
+                        }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) nh += __builtin_popcount(hit[i]);
             return;
         }
 #pragma unroll

@@ -280,6 +280,52 @@ def test_deterministic_repeat(pm):
     assert a[0].size > 100
 
 
+def _periodic(rnd, n, unit, start, length):
+    """A random text with `unit` repeated over [start, start + length)."""
+    text = random_text(rnd, n)
+    reps = np.frombuffer((unit * (length // len(unit) + 1)).encode(), dtype=np.uint8)[:length]
+    text[start:start + length] = reps
+    return text
+
+
+@pytest.mark.parametrize("unit_len,reps,k,region", [
+    (300, 2, 0, 20_000),     # m = 600: ~27 hits per tile, several lanes, wave-counted staging
+    (300, 2, 5, 20_000),
+    (40, 15, 2, 20_000),     # m = 600, a hit every 40 windows: > 32 per tile, the place kernel's re-scan
+    (1000, 5, 3, 30_000),    # m = 5000 (157 chunks)
+    (520, 1, 0, 600),        # m = 520 (17 chunks): one hit, verified by the whole wave
+    (16, 32, 1, 10_000),     # m = 512 (16 chunks): verified lane by lane
+])
+def test_long_pattern_hit_density(pm, unit_len, reps, k, region):
+    """Long patterns (the whole-wave exact counts) at controlled hit
+    densities, from one hit to more than a tile can stage: periodic text
+    regions make every window at a multiple of the period an exact copy."""
+    rnd = random.Random(unit_len * 1000 + reps * 10 + k)
+    unit = "".join(rnd.choice("ACGT") for _ in range(unit_len))
+    pat = list(unit * reps)
+    for j in rnd.sample(range(len(pat)), len(pat) // 10):  # classes that contain the base, and some Ns
+        pat[j] = {"A": "R", "G": "R", "C": "Y", "T": "Y"}[pat[j]] if rnd.random() < 0.7 else "N"
+    pat = "".join(pat)
+    text = _periodic(rnd, 200_000, unit, 50_000, region + len(pat))
+    t = pm.encode_text(text)
+    got = gpu_hits(pm, t, pm.Pattern(pat), k)
+    want = oracle_hits(text, pat, k)
+    assert want[0].size >= 1
+    assert_same(got, want, f"long pattern m={len(pat)} k={k}")
+
+
+def test_long_pattern_weak_filter(pm):
+    """A long pattern with few single-base positions and a large k: many
+    survivors in many lanes, so lanes verify their own (not the whole wave)."""
+    rnd = random.Random(99)
+    text = random_text(rnd, 300_000)
+    pat = "".join(rnd.choice("ACGT") if rnd.random() < 0.15 else rnd.choice("MRWSYKVHDBN") for _ in range(900))
+    for k in (40, 120):
+        plant_copies(rnd, text, pat, 5, k // 2)
+        t = pm.encode_text(text)
+        assert_same(gpu_hits(pm, t, pm.Pattern(pat), k), oracle_hits(text, pat, k), f"weak filter k={k}")
+
+
 # --- configured workloads -------------------------------------------------------------
 
 def test_small_workload(pm):
