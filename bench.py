@@ -244,6 +244,83 @@ def copy_calibration(gib: float = 1.0, reps: int = 3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def run_mscale(args):
+    """The shape of the paper's m-scaling experiment (Sect. 3, Tables 5-7)
+    on a synthetic text of chromosome 2's length: exact copies of m = 500,
+    10 000 and 100 000 cut at the tables' five sites per length, each
+    scanned in 5 timed runs (k = 0 unless --k).  Reports the mean and spread
+    per site and per length, and the slowest length's mean over the
+    fastest's."""
+    import numpy as np
+    import torch
+
+    from paper_1611_06115_amd import scan, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t0 = time.perf_counter()
+    w = synth.mscale(n=args.n or synth.CHR2_LEN)
+    k = args.k if args.k is not None else 0
+    log(f"[bench] generated {w.n} bases and {len(w.patterns)} cut patterns in {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream()
+    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
+    stream.synchronize()
+    text.check()
+    ws = scan.Workspace(dev, text.n, capacity=1 << 16)
+    runs = 5
+    rows = []
+    for pi, pat_s in enumerate(w.patterns):
+        pat = scan.Pattern(pat_s)
+        step = lambda: scan.scan_async(text, pat, k, ws)  # noqa: E731
+        for _ in range(max(1, args.warmup)):
+            step()
+        stream.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+        for a, b in ev:
+            a.record(stream)
+            step()
+            b.record(stream)
+        stream.synchronize()
+        t = np.array([a.elapsed_time(b) for a, b in ev])
+        _, kern = time_steps(step, 3, 0, stream, kernel=True)
+        hits = int(ws.n_hits.item())
+        pos = ws.pos[:min(hits, ws.capacity)].cpu().numpy()
+        site = w.plants[pi][1]
+        if not (pos == site).any():
+            raise SystemExit(f"cut site {site} of pattern {pi} (m={len(pat_s)}) not reported")
+        rows.append({"m": len(pat_s), "location": site + 1, "ms": round(float(t.mean()), 4),
+                     "sd": round(float(t.std()), 4), "kernel_ms": round(kern, 4), "hits": hits})
+        log(f"[bench] m={len(pat_s)} at {site + 1}: {t.mean():.4f} +- {t.std():.4f} ms, {hits} hits")
+    per_m = {}
+    for r in rows:
+        per_m.setdefault(r["m"], []).append(r["ms"])
+    per_m = {m: round(float(np.mean(v)), 4) for m, v in per_m.items()}
+    total_ms = sum(r["ms"] for r in rows)
+    kern_ms = sum(r["kernel_ms"] for r in rows)
+    comps = float(sum((text.n - r["m"] + 1) * r["m"] for r in rows))
+    achieved = 0.25 * text.n * len(rows) / (kern_ms / 1e3) / 1e9
+    result = {
+        "metric": "G base-pattern comparisons/sec",
+        "value": round(comps / (total_ms / 1e3) / 1e9, 1),
+        "unit": "G comparisons/s",
+        "n_gpus": 1, "steps": runs * len(rows), "warmup": args.warmup,
+        "ms_per_step": round(total_ms / len(rows), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bitwise (exact integer counts)", "data": "synthetic",
+        "config": {"workload": f"mscale: n={text.n} order-3 Markov GC 0.41 (chromosome 2's length), exact "
+                               f"copies of m = 500 / 10000 / 100000 at the 5 sites per length of Tables 5-7, k={k}",
+                   "per_m_ms": per_m,
+                   "slowest_over_fastest": round(max(per_m.values()) / min(per_m.values()), 4),
+                   "rows": rows},
+        # the count kernel over all runs: the text once per scan
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w.text, w.patterns[0], k, len(w.patterns[0]))
+    return result
+
+
 def run_batched(args):
     import numpy as np
     import torch
@@ -495,7 +572,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale"])
     ap.add_argument("--count", type=int, default=None, help="batched: number of patterns")
     ap.add_argument("--group", type=int, default=None, help="batched: patterns per text tile")
     ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
@@ -520,7 +597,7 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
               "by text range with an m-1 overlap and no exchange, see the design notes", flush=True)
         raise SystemExit(2)
-    run = {"batched": run_batched, "served": run_served}.get(args.workload, run_plain)
+    run = {"batched": run_batched, "served": run_served, "mscale": run_mscale}.get(args.workload, run_plain)
     res = run(args)
     print(json.dumps(res), flush=True)
 

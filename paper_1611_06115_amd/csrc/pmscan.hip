@@ -472,6 +472,50 @@ unsigned persistent_grid(ScanFn fn, uint64_t n_tiles) {
 
 uint64_t text_blocks(uint64_t n) { return ((n + 31) / 32 + kPadBlocks + 1) & ~1ull; }
 
+// Plans of long patterns are kept per host thread: building one takes
+// several passes over all m positions (~0.3 ms at m = 100 000, more than
+// the scan of a chromosome), and the same pattern is often scanned many
+// times.  An entry is used only for the same k and byte-for-byte the same
+// codes (other patterns differ within a few bytes, the match costs one
+// comparison of m bytes); its codes were checked when it was built.
+constexpr uint32_t kPlanCacheMinM = 4096;
+constexpr uint32_t kPlanCacheMaxM = 1u << 22;
+constexpr size_t kPlanCacheEntries = 16;
+struct PlanEntry {
+    uint32_t k = 0;
+    uint64_t used = 0;
+    std::vector<uint8_t> codes;
+    ScanPlan plan;
+};
+thread_local std::vector<PlanEntry> t_plans;
+thread_local uint64_t t_plan_clock = 0;
+
+// The plan of (codes, m, k), or PM_ERR_SYMBOL for a code above 15.
+pm_status scan_plan(const uint8_t* codes, uint32_t m, uint32_t k, ScanPlan& plan) {
+    const bool cache = m >= kPlanCacheMinM && m <= kPlanCacheMaxM;
+    if (cache)
+        for (PlanEntry& e : t_plans)
+            if (e.k == k && e.codes.size() == m && std::memcmp(e.codes.data(), codes, m) == 0) {
+                e.used = ++t_plan_clock;
+                plan = e.plan;
+                return PM_OK;
+            }
+    for (uint32_t j = 0; j < m; ++j)
+        if (codes[j] > 15) return fail(PM_ERR_SYMBOL, "pattern code above 15 at " + std::to_string(j));
+    plan = pm::build_plan(codes, m, k);
+    if (cache) {
+        if (t_plans.size() < kPlanCacheEntries) t_plans.emplace_back();
+        PlanEntry* slot = &t_plans[0];
+        for (PlanEntry& e : t_plans)
+            if (e.used < slot->used) slot = &e;
+        slot->k = k;
+        slot->used = ++t_plan_clock;
+        slot->codes.assign(codes, codes + m);
+        slot->plan = plan;
+    }
+    return PM_OK;
+}
+
 uint64_t max_tiles(uint64_t n) {
     // tiles of 64*kR blocks, starting at an even block at or below win_begin
     const uint64_t blocks = (n + 31) / 32 + 2;
@@ -636,13 +680,12 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
         return fail(PM_ERR_ARG, "image_dev must be 16-byte aligned");
     if (ws_bytes < pm_scan_workspace_bytes(n)) return fail(PM_ERR_WORKSPACE, "workspace too small");
     if (text_blocks(n) / 2 >= (1ull << 32)) return fail(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
-    for (uint32_t j = 0; j < m; ++j)
-        if (codes[j] > 15) return fail(PM_ERR_SYMBOL, "pattern code above 15 at " + std::to_string(j));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
     const uint64_t nw = m <= n ? n - m + 1 : 0;
     if (win_end > nw) win_end = nw;
-    const ScanPlan plan = pm::build_plan(codes, m, k);
+    ScanPlan plan;
+    if (const pm_status st = scan_plan(codes, m, k, plan); st != PM_OK) return st;
     if (win_begin >= win_end || plan.keff < 0) return fill_u64(n_hits_dev, 0, 1, s);
 
     const uint64_t wb0 = (win_begin >> 5) & ~1ull;

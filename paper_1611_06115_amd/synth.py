@@ -337,6 +337,36 @@ def genome(n: int = 3_100_000_000, m: int = 256, n_plants: int = 64,
     return Workload("genome", seed, n, text, [pat], [4], plants)
 
 
+# The m-scaling experiment of Sect. 3 (Tables 5-7): chromosome 2's length
+# and, per pattern length, the first printed location of each table row
+# (1-based; Table 5 row 1 prints its range in reverse order, and its lower
+# end is taken).
+CHR2_LEN = 243_199_373
+MSCALE_SITES = {
+    500: (150967401, 52803498, 8749475, 234748299, 90472976),
+    10000: (234097372, 33957613, 7034775, 115305600, 199419896),
+    100000: (234097372, 33957613, 7034775, 115305600, 199419896),
+}
+
+
+def mscale(n: int = CHR2_LEN) -> Workload:
+    """A chromosome-2-sized order-3 Markov text (GC 41%) and exact copies of
+    it of m = 500, 10 000 and 100 000, cut at the five sites per length that
+    Tables 5-7 list (0-based start = location - 1, moved left when the text
+    is shorter than the chromosome); plants are the cut sites (d = 0)."""
+    seed = SEED0 + 6
+    text = markov_text(n, seed)
+    pats, plants = [], []
+    for m, sites in MSCALE_SITES.items():
+        if m > n:
+            continue
+        for site in sites:
+            p0 = min(site - 1, n - m)
+            pats.append(text[p0:p0 + m].tobytes().decode())
+            plants.append((len(pats) - 1, p0, 0))
+    return Workload("mscale", seed, n, text, pats, [0] * len(pats), plants)
+
+
 def batched_patterns(count: int = 4096, seed: int = SEED0 + 3, m_lo: int = 16,
                      m_hi: int = 2048, k_hi: int = 8, dens_hi: float = 0.3):
     d = Draws(key(seed, STREAM_PATTERNS))

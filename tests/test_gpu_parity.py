@@ -396,3 +396,34 @@ def test_genome_workload_sampled(pm):
         want = oracle_hits(w.text, pat, k, win_begin=b, win_end=e)
         sel = (pos >= b) & (pos < e)
         assert_same((pos[sel], cnt[sel]), want, f"genome range {b},{e}")
+
+
+def test_mscale_workload(pm):
+    """The m-scaling workload at full size (a chromosome-2-sized Markov text,
+    exact copies of m = 500, 10 000 and 100 000 cut at the sites of the
+    paper's Tables 5-7): every pattern's list equals a full oracle scan and
+    contains its cut site with count 0."""
+    from paper_1611_06115_amd import synth
+
+    w = synth.mscale()
+    say(f"mscale: n={w.n}, {len(w.patterns)} patterns")
+    t = pm.encode_text(w.text)
+    for (pi, site, _), pat in zip(w.plants, w.patterns):
+        got = gpu_hits(pm, t, pm.Pattern(pat), 0)
+        assert_same(got, oracle_hits(w.text, pat, 0), f"mscale pattern {pi} m={len(pat)}")
+        assert site in set(got[0].tolist()) and dict(zip(got[0].tolist(), got[1].tolist()))[site] == 0
+
+
+def test_long_pattern_plan_reuse(pm):
+    """Long patterns' plans are kept between calls: the same pattern at
+    another k, and a pattern that differs only in its last position, must
+    not reuse a plan built for something else."""
+    rnd = random.Random(4096)
+    text = random_text(rnd, 400_000)
+    a = rand_pattern(rnd, 5000, 0.1, "ACGTRYN")
+    b = a[:-1] + ("A" if a[-1] != "A" else "C")
+    plant_copies(rnd, text, a, 3, 2)
+    plant_copies(rnd, text, b, 3, 0)
+    t = pm.encode_text(text)
+    for pat, k in ((a, 0), (b, 0), (a, 2), (b, 3), (a, 0), (b, 0)):
+        assert_same(gpu_hits(pm, t, pm.Pattern(pat), k), oracle_hits(text, pat, k), f"reuse k={k} {pat == a}")
