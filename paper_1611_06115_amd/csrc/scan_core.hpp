@@ -206,14 +206,15 @@ __device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* _
 }
 
 // Exact count of window s by the whole wave (every lane active): lane l
-// takes the chunks of 32 positions l, l + 64, ..., one per round; the wave's
-// sum is tested against `limit` after each round.  Returns the same value in every lane (exact when <= limit).
+// takes the chunks of 32 positions l, l + 64, ..., four per round with their
+// loads issued together; the wave's sum is tested against `limit` after each
+// round.  Returns the same value in every lane (exact when <= limit).
 __device__ uint32_t count_window_wave(const uint4* __restrict__ text4, const uint4* __restrict__ image,
                                       uint32_t nchunks, uint64_t s, uint32_t limit, uint32_t lane) {
     const uint2* text = reinterpret_cast<const uint2*>(text4);
     const uint64_t q = s >> 5;
     const uint32_t r = (uint32_t)s & 31u;
-    constexpr uint32_t V = 1;
+    constexpr uint32_t V = 4;
     uint32_t total = 0;
     for (uint32_t c0 = 0; c0 < nchunks; c0 += 64 * V) {
         uint2 w0[V], w1[V];
