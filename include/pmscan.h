@@ -128,6 +128,25 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
                   void* ws_dev, uint64_t ws_bytes, void* stream);
 
+/* Scan of a text kept in host memory (Sect. 2.6's split into pieces with an
+ * m-1 overlap).  ascii_host: n bases of A/C/G/T (either case) in host
+ * memory; allocated with hipHostMalloc (pinned) the copies run at the full
+ * speed of the link, pageable memory works more slowly.  The windows are cut
+ * into chunks of chunk_bases windows; each chunk's bases (with the m-1 that
+ * follow) are copied into one of two device buffers on copy_stream while the
+ * previous chunk is encoded and scanned on `stream`.  Results equal pm_scan
+ * over the whole text: ascending text positions and exact counts, the first
+ * `capacity` hits in pos_dev / cnt_dev, *n_hits_dev = the total.  ws_dev:
+ * 256-byte aligned, at least pm_scan_host_workspace_bytes(chunk_bases, m)
+ * bytes.  A byte other than A/C/G/T gives PM_ERR_SYMBOL (the detail names
+ * its index).  Returns when the scan is complete (it waits for both
+ * streams); the host text must stay valid until then. */
+uint64_t pm_scan_host_workspace_bytes(uint64_t chunk_bases, uint32_t m);
+pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* codes, uint32_t m,
+                       uint32_t k, const void* image_dev, uint64_t chunk_bases, int64_t* pos_dev,
+                       uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev, void* ws_dev,
+                       uint64_t ws_bytes, void* stream, void* copy_stream);
+
 /* Measurement hook: the next pm_scan or pm_scan_batch call made by this
  * thread records ev_begin on its stream right before its main kernel launch
  * (the count kernel; the batched kernels) and ev_end right after it, so that

@@ -52,6 +52,8 @@ def lib():
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
                               i32),
             "pm_time_next_scan": ([vp, vp], i32),
+            "pm_scan_host_workspace_bytes": ([u64, u32], u64),
+            "pm_scan_host": ([vp, u64, vp, u32, u32, vp, u64, vp, vp, u64, vp, vp, u64, vp, vp], i32),
             "pm_server_now_ns": ([], u64),
             "pm_server_min_arena_bytes": ([u64, vp], u64),
             "pm_server_create": ([vp, u64, vp, u64, vp, vp, vp], i32),
@@ -223,6 +225,50 @@ def scan_async(text: Text, pattern: Pattern, k: int, ws: Workspace, win_begin: i
         ctypes.c_void_p(ws.pos.data_ptr()), ctypes.c_void_p(ws.cnt.data_ptr()), ws.capacity,
         ctypes.c_void_p(ws.n_hits.data_ptr()), ctypes.c_void_p(ws.ws.data_ptr()), ws.ws.numel(),
         _stream(stream)))
+
+
+def scan_host_workspace_bytes(chunk_bases: int, m: int) -> int:
+    return int(lib().pm_scan_host_workspace_bytes(int(chunk_bases), int(m)))
+
+
+def scan_host(host_text, pattern: Pattern | str, k: int, chunk_bases: int = 1 << 27, capacity: int = 1 << 16,
+              device=None, stream=None, copy_stream=None):
+    """Scan a text that stays in host memory (a uint8 numpy array or CPU
+    tensor of ASCII bases; pinned memory, e.g. torch.empty(..., pin_memory=
+    True), copies fastest), streamed through the device in chunks of
+    `chunk_bases` windows.  Returns (positions int64, counts uint16) device
+    tensors equal to scan() of the encoded text; re-runs with an exact
+    buffer when the hits exceed `capacity`."""
+    import torch
+
+    if isinstance(pattern, str):
+        pattern = Pattern(pattern)
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    if isinstance(host_text, torch.Tensor):
+        if host_text.device.type != "cpu" or host_text.dtype != torch.uint8 or not host_text.is_contiguous():
+            raise ValueError("host_text must be a contiguous uint8 CPU tensor")
+        ptr, n = host_text.data_ptr(), host_text.numel()
+    else:
+        host_text = np.ascontiguousarray(host_text, dtype=np.uint8)
+        ptr, n = host_text.ctypes.data, host_text.size
+    chunk_bases = max(1, min(int(chunk_bases), n))
+    stream = stream or torch.cuda.current_stream(dev)
+    copy_stream = copy_stream or torch.cuda.Stream(dev)
+    ws = torch.empty(scan_host_workspace_bytes(chunk_bases, pattern.m), dtype=torch.uint8, device=dev)
+    img = pattern.image(dev)
+    n_hits = torch.zeros(1, dtype=torch.int64, device=dev)
+    while True:
+        pos = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+        cnt = torch.empty(max(capacity, 1), dtype=torch.uint16, device=dev)
+        check(lib().pm_scan_host(
+            ctypes.c_void_p(ptr), n, pattern.codes.ctypes.data, pattern.m, int(k), ctypes.c_void_p(img.data_ptr()),
+            int(chunk_bases), ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(cnt.data_ptr()), int(capacity),
+            ctypes.c_void_p(n_hits.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+            _stream(stream), _stream(copy_stream)))
+        total = int(n_hits.item())
+        if total <= capacity:
+            return pos[:total], cnt[:total]
+        capacity = total
 
 
 def scan(text: Text, pattern: Pattern | str, k: int, win_begin: int = 0, win_end: int | None = None,
