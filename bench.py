@@ -392,6 +392,8 @@ def run_outofcore(args):
         "roofline": {"bound": "link", "achieved": round(moved / sec / 1e9, 2), "peak": round(moved / copy_sec / 1e9, 2),
                      "unit": "GB/s", "frac": round(copy_sec / sec, 4), "traffic": None},
     }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w.text, pattern, k, m)
     return result
 
 
