@@ -122,7 +122,9 @@ uint64_t pm_scan_workspace_bytes(uint64_t n);
  * ws_dev: device workspace of at least pm_scan_workspace_bytes(n) bytes; it
  * needs no initialisation, holds nothing between calls, and must not be used
  * by two calls that can run at the same time.  m > n gives 0 hits.
- * Asynchronous on `stream`. */
+ * Asynchronous on `stream`.  The filter plan of a pattern of 4096 positions
+ * or more is kept for the calling thread (up to 16 plans, each with a copy of
+ * its codes, used again only for the same k and identical codes). */
 pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m,
                   uint32_t k, const void* image_dev, uint64_t win_begin, uint64_t win_end,
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
