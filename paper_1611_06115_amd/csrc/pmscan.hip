@@ -266,6 +266,7 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
     const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * a.n_tiles / gridDim.x);
     uint32_t tile = (uint32_t)((uint64_t)blockIdx.x * a.n_tiles / gridDim.x) + wv;
     uint32_t sum = 0;
+    __shared__ unsigned long long s_vh[TPB / 64][kWaveHits];  // hits kept by tile_filter, per wave
     // the text of the wave's next tile is loaded while this one is computed
     uint4 nxt[(R + 2) / 2];
     if (tile < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile, R), nxt);
@@ -283,7 +284,8 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
         uint32_t hit[R], nh;
         Lane<R> s;
         make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
+        uint32_t nvh = 0;
+        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh, s_vh[wv], &nvh);
         if (__ballot(nh != 0) == 0) {  // the usual case: no hits in the tile
             if (lane == 0) a.counts[tile] = 0;
             continue;
@@ -295,9 +297,17 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
         if (total > (uint32_t)kCap) continue;
         const uint64_t base = 32 * T0;
         if (!EXH && p.nchunks > kWaveVerifyChunks) {
-            // long patterns: the hits in position order (the staging order),
-            // each counted by the whole wave and written by its lane
             unsigned long long* out = a.staged + (uint64_t)tile * kCap;
+            if (nvh == total && total <= kWaveHits) {
+                // every hit was counted by the whole wave and kept, in order
+                if (lane < total) {
+                    const unsigned long long v = s_vh[wv][lane];
+                    out[lane] = (((v >> 16) - base) << 16) | (v & 0xFFFFu);
+                }
+                continue;
+            }
+            // otherwise: the hits in position order (the staging order), each
+            // counted by the whole wave and written by its lane
             for (uint32_t j = 0;; ++j) {
                 uint32_t mine = 0;
 #pragma unroll

@@ -253,6 +253,9 @@ __device__ uint32_t count_window_wave(const uint4* __restrict__ text4, const uin
 // otherwise each lane verifies its own survivors.
 constexpr uint32_t kWaveVerifyChunks = 16;
 constexpr int kWaveVerifyLanes = 4;
+// Hits found by the whole wave that are kept for the output (so that they
+// need not be counted again).
+constexpr uint32_t kWaveHits = 8;
 
 // The lane's text planes for blocks B+fw .. B+fw+R+1 (the 16-byte groups in
 // t) and, for each base c with bit c of `singles` set, its mismatch plane:
@@ -286,7 +289,8 @@ __device__ __forceinline__ void make_lane(const uint4 (&t)[(R + 2) / 2], uint32_
 template <int R, int L, bool EXH, bool WV, class Plan>
 __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
                                             const Lane<R>& s, Counters<R, L>& C, uint32_t (&hit)[R],
-                                            uint32_t& nh) {
+                                            uint32_t& nh, unsigned long long* vh = nullptr,
+                                            uint32_t* nvh = nullptr) {
     // ---- valid windows of each lane word ------------------------------------
     // (windows outside [win_begin, win_end) start dead; `interior` says the
     // whole tile lies inside, which holds for all tiles but the edge ones)
@@ -370,6 +374,7 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, u
         uint32_t any = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i) any |= ~C.dead[i];
+        if (vh) *nvh = 0;
         if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
 #pragma unroll
             for (int i = 0; i < R; ++i) hit[i] = 0;
@@ -409,6 +414,12 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, u
                             C.dead[i] |= 1u << fb;
                             if (c <= p.k) hit[i] |= 1u << fb;
                         }
+                }
+                // hits come in position order: the first kWaveHits are kept
+                // (position << 16 | count) for the caller's output
+                if (vh && c <= p.k) {
+                    if (*nvh < kWaveHits && lane == owner) vh[*nvh] = (pos << 16) | c;
+                    ++*nvh;
                 }
             }
 #pragma unroll
