@@ -42,7 +42,7 @@ typedef int32_t pm_status;
 #define PM_ERR_SYMBOL (-2)      /* pattern symbol outside Table 2 / malformed class        */
 #define PM_ERR_HIP (-3)         /* a HIP runtime call failed                                */
 #define PM_ERR_WORKSPACE (-4)   /* workspace or output buffer smaller than required         */
-#define PM_ERR_UNSUPPORTED (-5) /* valid request this build cannot serve                    */
+#define PM_ERR_UNSUPPORTED (-5) /* valid request the library does not support              */
 #define PM_ERR_BUSY (-6)        /* serving engine: no free slot or memory for the query     */
 #define PM_ERR_NOT_FOUND (-7)   /* serving engine: unknown query id                          */
 
