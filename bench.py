@@ -530,7 +530,8 @@ def run_served(args):
     text = scan.encode_text(torch.from_numpy(w.text).to(dev))
     torch.cuda.synchronize()
     text.check()
-    cfg = server.ServerConfig(chunks=args.chunks or 0, max_active=args.slots or 0)
+    cfg = server.ServerConfig(chunks=args.chunks or 0, max_active=args.slots or 0,
+                              batch=scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0))
     srv = server.Server(text, int(args.arena_gib * (1 << 30)), cfg)
     for i in range(4):  # warm-up through the whole path (not timed)
         srv.result(srv.submit(pats[i], w.ks[i]))
@@ -650,7 +651,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale", "outofcore"])
     ap.add_argument("--count", type=int, default=None, help="batched: number of patterns")
-    ap.add_argument("--group", type=int, default=None, help="batched: patterns per text tile")
+    ap.add_argument("--group", type=int, default=None, help="batched, served: patterns per text tile")
     ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
     ap.add_argument("--lane-words", type=int, default=None, help="batched: 4 or 6")
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch shape now")
