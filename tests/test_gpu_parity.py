@@ -427,3 +427,40 @@ def test_long_pattern_plan_reuse(pm):
     t = pm.encode_text(text)
     for pat, k in ((a, 0), (b, 0), (a, 2), (b, 3), (a, 0), (b, 0)):
         assert_same(gpu_hits(pm, t, pm.Pattern(pat), k), oracle_hits(text, pat, k), f"reuse k={k} {pat == a}")
+
+
+def test_text_beyond_2_32_bases(pm):
+    """A 4.4e9-base text: windows past 2^32 (one straddling it, one just after
+    it, the very last one) are found with their counts by the plain and the
+    batched scan, and both equal the oracle on ranges around them."""
+    from paper_1611_06115_amd import synth
+
+    n = 4_400_000_000
+    rnd = random.Random(2 ** 32)
+    text = synth.iid_text(n, seed=synth.SEED0 + 90)
+    pat = rand_pattern(rnd, 100, 0.2, "ACGTRYN")
+    sites = [(1 << 32) - 50, (1 << 32) + 12_345, n - 100]
+    from oracle import reference as ref
+
+    for p0 in sites:
+        for j, cls in enumerate(ref.parse(pat)):
+            text[p0 + j] = ord(rnd.choice(sorted(cls)))
+    say(f"text of {n} bases, plants at {sites}")
+    ascii_dev = torch.from_numpy(text).cuda()
+    t = pm.encode_text(ascii_dev)
+    torch.cuda.synchronize()
+    t.check()
+    del ascii_dev
+    torch.cuda.empty_cache()
+    k = 3
+    plain = gpu_hits(pm, t, pm.Pattern(pat), k)
+    batch = pm.scan_batch(t, [pat, "ACGTACGTACGTACGTACGTACGT"], [k, 2])[0]
+    batch = (batch[0].cpu().numpy(), batch[1].cpu().numpy())
+    assert_same(batch, plain, "batched vs plain")
+    found = dict(zip(plain[0].tolist(), plain[1].tolist()))
+    for p0 in sites:
+        assert found.get(p0) == 0, p0
+        b, e = max(0, p0 - 1_000_000), min(n - len(pat) + 1, p0 + 1_000_000)
+        sel = (plain[0] >= b) & (plain[0] < e)
+        assert_same((plain[0][sel], plain[1][sel]), oracle_hits(text, pat, k, win_begin=b, win_end=e),
+                    f"range around {p0}")
