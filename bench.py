@@ -65,6 +65,20 @@ def measured_traffic(workload: str):
     return t.get("hbm_bytes_per_launch")
 
 
+def measured_count_valu(workload: str):
+    """VALU lane-ops per count-kernel launch from the committed counter run
+    (SQ_INSTS_VALU x 64), or None when absent or taken on a different kernel
+    source."""
+    path = os.path.join(PROFILE_DIR, f"scan_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_sha") != kernel_source_sha(workload):
+        return None
+    return t.get("count_kernel_valu_lane_ops")
+
+
 def valu_profile(workload: str):
     """The committed VALU counter run of a workload ({"config": launch shape,
     "valu_lane_ops_per_launch": ...}), or None when absent or taken on a
@@ -205,6 +219,7 @@ def run_plain(args):
     algo_bytes = 0.25 * text.n + 8.0 * hits + pat.image(dev).numel() * 4
     achieved = algo_bytes / (kern_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload)
+    valu_ops = measured_count_valu(args.workload)
     result = {
         "metric": "G base-pattern comparisons/sec",
         "value": round(comps / sec / 1e9, 2),
@@ -219,7 +234,13 @@ def run_plain(args):
         "dtype": "u32 bitwise (exact integer counts)",
         "data": "synthetic",
         "config": {"workload": desc, "n": text.n, "m": m, "k": k, "windows": nw, "hits": hits,
-                   "windows_per_s": round(nw / sec, 1), "encode_kernel_ms": round(enc_ms, 4)},
+                   "windows_per_s": round(nw / sec, 1), "encode_kernel_ms": round(enc_ms, 4),
+                   # the same kernel against the int32 VALU peak (its lane-ops
+                   # per launch from the committed counter run)
+                   "count_kernel_valu": None if valu_ops is None else {
+                       "achieved": round(valu_ops / (kern_ms / 1e3) / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                       "unit": "T int32 VALU lane-ops/s",
+                       "frac": round(valu_ops / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
