@@ -376,15 +376,27 @@ def run_outofcore(args):
     # the same bytes copied alone, chunk by chunk, on one stream
     buf = torch.empty(chunk + len(pattern) - 1, dtype=torch.uint8, device=dev)
     copy_times = []
-    for _ in range(reps):
+    for rep in range(reps + 1):  # the first pass is a warm-up
         stream.synchronize()
         t1 = time.perf_counter()
         for first in range(0, n - len(pattern) + 1, chunk):
             ln = min(n, first + chunk + len(pattern) - 1) - first
             buf[:ln].copy_(host[first:first + ln], non_blocking=True)
         stream.synchronize()
-        copy_times.append(time.perf_counter() - t1)
+        if rep > 0:
+            copy_times.append(time.perf_counter() - t1)
     copy_sec = float(np.mean(copy_times))
+    # the count kernel of the first chunk, timed by the library's hook (it
+    # brackets the next pm_scan call made by this thread)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    e1.record(stream)
+    stream.synchronize()
+    scan.time_next_scan(e0, e1)
+    scan.scan_host(host, pat, k, chunk_bases=chunk, stream=stream, copy_stream=copy_stream)
+    kern_ms = e0.elapsed_time(e1)
+    chunk_len = min(n, chunk + len(pattern) - 1)
+    achieved = 0.25 * chunk_len / (kern_ms / 1e3) / 1e9
     hits = int(pos.numel())
     found = dict(zip(pos.cpu().tolist(), cnt.cpu().tolist()))
     missed = [(p, d) for q, p, d in w.plants if d <= k and found.get(p) != d]
@@ -394,7 +406,7 @@ def run_outofcore(args):
     comps = float(n - m + 1) * m
     moved = float(n + (len(range(0, n - m + 1, chunk)) - 1) * (m - 1))
     log(f"[bench] {reps} runs, {sec * 1e3:.1f} ms per scan from host memory, copies alone {copy_sec * 1e3:.1f} ms, "
-        f"{hits} hits")
+        f"{hits} hits; a chunk's count kernel {kern_ms:.3f} ms")
     result = {
         "metric": "G base-pattern comparisons/sec",
         "value": round(comps / sec / 1e9, 1),
@@ -405,13 +417,15 @@ def run_outofcore(args):
         "config": {"workload": f"outofcore: the genome workload (n={n}, m={m}, k={k}) with the ASCII text in "
                                f"pinned host memory, streamed in chunks of {chunk} windows",
                    "hits": hits, "chunk_bases": chunk,
-                   "host_to_device_GBps": round(moved / sec / 1e9, 2),
-                   "copy_alone_ms": round(copy_sec * 1e3, 3),
-                   "copy_alone_GBps": round(moved / copy_sec / 1e9, 2)},
-        # the bound is the host-to-device link: measured against the same
-        # copies alone
-        "roofline": {"bound": "link", "achieved": round(moved / sec / 1e9, 2), "peak": round(moved / copy_sec / 1e9, 2),
-                     "unit": "GB/s", "frac": round(copy_sec / sec, 4), "traffic": None},
+                   # the pace is the host-to-device link: the chunks with
+                   # their overlaps over the scan's time, against the same
+                   # copies alone
+                   "link": {"achieved": round(moved / sec / 1e9, 2), "copies_alone": round(moved / copy_sec / 1e9, 2),
+                            "unit": "GB/s", "frac": round(copy_sec / sec, 4),
+                            "copies_alone_ms": round(copy_sec * 1e3, 3)}},
+        # the dominant kernel: the count kernel of one chunk
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
     }
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w.text, pattern, k, m)

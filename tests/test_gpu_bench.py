@@ -55,6 +55,19 @@ def test_bench_served_contract():
     assert r["config"]["queries"] > 50
 
 
+def test_bench_mscale_and_outofcore_contract():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "mscale", "--n", "2000000", "--warmup", "1", "--no-cpu-baseline")
+    check_contract(r)
+    assert set(r["config"]["per_m_ms"]) == {"500", "10000", "100000"} and len(r["config"]["rows"]) == 15
+    r = run_bench("--workload", "outofcore", "--n", "40000000", "--chunk", "5000000", "--steps", "2")
+    check_contract(r)
+    link = r["config"]["link"]
+    assert link["achieved"] > 0 and link["copies_alone"] > 0 and 0 < link["frac"] <= 1.5
+    assert r["cpu_baseline"]["kind"] == "oracle"
+
+
 def test_time_next_scan_brackets_the_count_kernel():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
