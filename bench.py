@@ -128,6 +128,18 @@ def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
     return step_ms, sum(a.elapsed_time(b) for a, b in pairs) / steps
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0):
     """The oracle (plain brute force with early stop, all host threads up to
     16) on a prefix of the windows, sized to about target_s seconds."""
@@ -148,7 +160,7 @@ def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0):
         "value": round(sample * m / dt / 1e9, 3),
         "unit": "G comparisons/s",
         "cores": threads,
-        "kind": "oracle",
+        "kind": "oracle", "cpu": host_cpu_model(),
         "sample": f"windows [0, {sample}) of the same text ({sample / nw:.1%} of the pass), "
                   f"k={k}, {dt:.1f} s wall, {hits} hits",
     }
@@ -534,7 +546,7 @@ def run_batched(args):
                 break
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(comps_cpu / dt / 1e9, 3), "unit": "G comparisons/s",
-                                  "cores": threads, "kind": "oracle",
+                                  "cores": threads, "kind": "oracle", "cpu": host_cpu_model(),
                                   "sample": f"first {done} patterns, windows [0, {win}) each, {dt:.1f} s"}
     return result
 
@@ -674,7 +686,7 @@ def run_served(args):
                 break
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(comps_cpu / dt / 1e9, 3), "unit": "G comparisons/s",
-                                  "cores": threads, "kind": "oracle",
+                                  "cores": threads, "kind": "oracle", "cpu": host_cpu_model(),
                                   "sample": f"first {done} pool queries, windows [0, {win}) each, {dt:.1f} s"}
     return result
 
