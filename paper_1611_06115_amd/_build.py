@@ -32,5 +32,19 @@ def build(extra: list[str] | None = None, out: str = LIB) -> str:
     return out
 
 
+def build_c_client() -> str:
+    """The test client that uses only the C ABI (tests/c_client), linked to
+    the library in place."""
+    src = os.path.join(HERE, "..", "tests", "c_client", "pm_client.cpp")
+    out = os.path.join(HERE, "..", "tests", "c_client", "pm_client")
+    if not os.path.exists(src):
+        return ""
+    cmd = [HIPCC, "-O2", "-std=c++17", "-Wall", "-I", os.path.join(HERE, "..", "include"), src,
+           "-L", HERE, "-lpmscan", "-Wl,-rpath,$ORIGIN/../../paper_1611_06115_amd", "-o", out + ".tmp"]
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(sys.argv[1:]))
