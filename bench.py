@@ -358,8 +358,8 @@ def run_outofcore(args):
     """The genome workload with the text kept in pinned host memory and
     scanned by streaming it through the device in chunks with an m-1 overlap
     (copies on a second stream overlapping the scans).  The link sets the
-    pace, so the line reports the end-to-end rate next to a plain pinned
-    host-to-device copy of the same bytes in the same chunk sizes."""
+    pace, so the line reports the end-to-end rate next to one plain pinned
+    host-to-device copy of the whole text."""
     import numpy as np
     import torch
 
@@ -385,18 +385,18 @@ def run_outofcore(args):
         pos, cnt = scan.scan_host(host, pat, k, chunk_bases=chunk, stream=stream, copy_stream=copy_stream)
         times.append(time.perf_counter() - t1)
     sec = float(np.mean(times))
-    # the same bytes copied alone, chunk by chunk, on one stream
-    buf = torch.empty(chunk + len(pattern) - 1, dtype=torch.uint8, device=dev)
+    # the link alone: one host-to-device copy of the whole text (after a
+    # warm-up copy), the rate the chunks cannot beat
+    whole = torch.empty(n, dtype=torch.uint8, device=dev)
     copy_times = []
-    for rep in range(reps + 1):  # the first pass is a warm-up
+    for rep in range(reps + 1):
         stream.synchronize()
         t1 = time.perf_counter()
-        for first in range(0, n - len(pattern) + 1, chunk):
-            ln = min(n, first + chunk + len(pattern) - 1) - first
-            buf[:ln].copy_(host[first:first + ln], non_blocking=True)
+        whole.copy_(host, non_blocking=True)
         stream.synchronize()
         if rep > 0:
             copy_times.append(time.perf_counter() - t1)
+    del whole
     copy_sec = float(np.mean(copy_times))
     # the count kernel of the first chunk, timed by the library's hook (it
     # brackets the next pm_scan call made by this thread)
@@ -417,7 +417,7 @@ def run_outofcore(args):
     m = len(pattern)
     comps = float(n - m + 1) * m
     moved = float(n + (len(range(0, n - m + 1, chunk)) - 1) * (m - 1))
-    log(f"[bench] {reps} runs, {sec * 1e3:.1f} ms per scan from host memory, copies alone {copy_sec * 1e3:.1f} ms, "
+    log(f"[bench] {reps} runs, {sec * 1e3:.1f} ms per scan from host memory, the text copied alone {copy_sec * 1e3:.1f} ms, "
         f"{hits} hits; a chunk's count kernel {kern_ms:.3f} ms")
     result = {
         "metric": "G base-pattern comparisons/sec",
@@ -432,9 +432,9 @@ def run_outofcore(args):
                    # the pace is the host-to-device link: the chunks with
                    # their overlaps over the scan's time, against the same
                    # copies alone
-                   "link": {"achieved": round(moved / sec / 1e9, 2), "copies_alone": round(moved / copy_sec / 1e9, 2),
-                            "unit": "GB/s", "frac": round(copy_sec / sec, 4),
-                            "copies_alone_ms": round(copy_sec * 1e3, 3)}},
+                   "link": {"achieved": round(moved / sec / 1e9, 2), "copy_alone": round(n / copy_sec / 1e9, 2),
+                            "unit": "GB/s", "frac": round((moved / sec) / (n / copy_sec), 4),
+                            "copy_alone_ms": round(copy_sec * 1e3, 3)}},
         # the dominant kernel: the count kernel of one chunk
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},

@@ -64,7 +64,7 @@ def test_bench_mscale_and_outofcore_contract():
     r = run_bench("--workload", "outofcore", "--n", "40000000", "--chunk", "5000000", "--steps", "2")
     check_contract(r)
     link = r["config"]["link"]
-    assert link["achieved"] > 0 and link["copies_alone"] > 0 and 0 < link["frac"] <= 1.5
+    assert link["achieved"] > 0 and link["copy_alone"] > 0 and 0 < link["frac"] <= 1.5
     assert r["cpu_baseline"]["kind"] == "oracle"
 
 
