@@ -222,7 +222,7 @@ pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const 
 typedef struct pm_server pm_server;
 
 typedef struct {
-    uint32_t chunks;          /* window ranges per revolution of the text; 0 = 8      */
+    uint32_t chunks;          /* window ranges per revolution of the text; 0 = 1      */
     uint32_t max_active;      /* queries scanned together (slots); 0 = 1024           */
     uint64_t workspace_bytes; /* arena bytes kept for the batch workspace; 0 = 1/4   */
     pm_batch_config batch;    /* shape of the batched launches; zeros = defaults.     */
@@ -254,8 +254,8 @@ typedef struct {
     uint64_t submitted, admitted, completed, failed;
     uint64_t reruns;
     uint64_t comparisons;     /* sum over completed queries of (n - m + 1) * m           */
-    uint32_t active, waiting; /* now                                                      */
-    uint32_t peak_active;
+    uint32_t active, waiting; /* now: admitted and not complete; not admitted yet      */
+    uint32_t peak_active;     /* most queries in one chunk step (at most max_active)     */
     uint32_t chunks;
     uint64_t hit_slots;       /* hit slots (10 bytes each) in the arena                  */
     uint64_t hit_slots_used, hit_slots_peak;

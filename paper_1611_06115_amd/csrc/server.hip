@@ -1,8 +1,10 @@
 // server.hip -- query server over a text resident in HBM (libpmscan).
 //
 // Continuous batching of a scan.  A scan has no natural iteration, so the
-// server makes one: the window range [0, n) is cut into C chunks, and the
-// engine thread runs chunk steps over chunks 0, 1, ..., C-1, 0, 1, ...  A
+// server makes one: the window range [0, n) is cut into C chunks (one by
+// default: a step's fixed costs make fewer, longer steps give the lower
+// latency), and the engine thread runs chunk steps over chunks 0, 1, ...,
+// C-1, 0, 1, ...  A
 // step is one batched launch over its chunk for every admitted query.  A
 // query is admitted between steps (in arrival order, while a slot and arena
 // memory are free), enters at whatever chunk comes next, and is complete
@@ -224,7 +226,7 @@ struct pm_server {
     int device = 0;
     const void* text = nullptr;
     uint64_t n = 0;
-    uint32_t C = 8, max_active = 1024;
+    uint32_t C = 1, max_active = 1024;
     uint64_t W = 0;  // windows per chunk
     // Admission sizes the workspace with bcfg.  When the caller left the
     // sub-range count to the library, bcfg holds the floor kAdmitSubRanges
@@ -281,11 +283,15 @@ struct pm_server {
     // ----------------------------------------------------------------------
     void publish(Query* q, int32_t state, int32_t error) {
         std::lock_guard<std::mutex> lk(mu);
+        // admitted and not complete: counted here rather than from the step
+        // set, which a query leaves once its last chunk step is launched
+        if (q->state == PM_QUERY_ACTIVE && state != PM_QUERY_ACTIVE) --st.active;
         q->state = state;
         q->error = error;
         if (state == PM_QUERY_ACTIVE) {
             q->admit_ns = clock_ns();
             ++st.admitted;
+            ++st.active;
         } else if (state == PM_QUERY_DONE) {
             q->complete_ns = clock_ns();
             ++st.completed;
@@ -442,6 +448,10 @@ struct pm_server {
                     "hipMemcpyAsync") ||
             !hip_ok(hipEventRecord(step_ev[slot], main), "hipEventRecord"))
             return false;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            st.peak_active = std::max(st.peak_active, count);
+        }
         Step stp;
         stp.chunk = chunk;
         stp.slot = slot;
@@ -563,8 +573,16 @@ struct pm_server {
                 later.push_back(q);
                 continue;
             }
+            // segments already one after another from the region's start
+            // (always with one chunk): the result is where it is
+            bool contiguous = in_place;
+            for (uint64_t c = 0, d0 = 0; c < C && contiguous; ++c) {
+                const uint64_t src = q->extra[c] != kNone ? q->extra[c] : q->region + c * q->cap;
+                if (q->hits[c] && src != q->region + d0) contiguous = false;
+                d0 += q->hits[c];
+            }
             uint64_t base = q->region;
-            bool separate = !in_place || total >= kBigJoin;
+            bool separate = !contiguous && (!in_place || total >= kBigJoin);
             if (separate) {
                 q->result = hit_pool.alloc(total);
                 if (q->result == kNone) {
@@ -691,9 +709,7 @@ struct pm_server {
 
     void update_stats() {
         std::lock_guard<std::mutex> lk(mu);
-        st.active = (uint32_t)active.size();
         st.waiting = (uint32_t)(waiting.size() + incoming.size());
-        st.peak_active = std::max<uint32_t>(st.peak_active, st.active);
         st.hit_slots_used = hit_pool.used();
         st.hit_slots_peak = hit_pool.peak();
     }
@@ -804,7 +820,7 @@ ArenaPlan plan_arena(uint64_t n, uint64_t arena_bytes, uint32_t C, uint32_t max_
 
 void normalise(const pm_server_config* cfg, uint64_t arena_bytes, uint32_t& C, uint32_t& max_active,
                uint64_t& ws_bytes, pm_batch_config& b, bool* adaptive = nullptr) {
-    C = cfg && cfg->chunks ? cfg->chunks : 8;
+    C = cfg && cfg->chunks ? cfg->chunks : 1;
     max_active = cfg && cfg->max_active ? cfg->max_active : 1024;
     ws_bytes = cfg && cfg->workspace_bytes ? cfg->workspace_bytes : align256(arena_bytes / 4);
     std::memset(&b, 0, sizeof(b));
@@ -904,6 +920,7 @@ pm_status pm_server_create(const void* text_dev, uint64_t n, void* arena_dev, ui
             std::lock_guard<std::mutex> lk(raw->mu);
             for (auto& kv : raw->queries)
                 if (kv.second->state < PM_QUERY_DONE) {
+                    if (kv.second->state == PM_QUERY_ACTIVE) --raw->st.active;
                     kv.second->state = PM_QUERY_FAILED;
                     kv.second->error = PM_ERR_HIP;
                 }

@@ -105,7 +105,7 @@ def test_served_under_memory_pressure(pm, served_text):
         res = collect(srv, ids)
         st = srv.stats()
     say(f"  stats {st}")
-    assert st["peak_active"] <= 3
+    assert 1 <= st["peak_active"] <= 3 and st["active"] == 0
     assert st["completed"] == len(sub)
     for j, i in enumerate(sub):
         assert_same(res[j], alone(scan, t, pats[i], ks[i]), f"pressure query {i}")
@@ -249,4 +249,5 @@ def test_served_genome_scale(pm):
         st = srv.stats()
     say(f"  stats {st}")
     assert st["completed"] >= len(qs) and st["failed"] == 0
+    assert st["active"] == 0 and 1 <= st["peak_active"] <= 1024
     assert checked == 16
