@@ -55,12 +55,13 @@ def collect(srv, ids):
     return out
 
 
-def test_served_equals_alone_and_oracle(pm, served_text):
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_served_equals_alone_and_oracle(pm, served_text, chunks):
     scan, server = pm
     text, pats, ks, plants = served_text
     t = scan.encode_text(text)
-    cfg = server.ServerConfig(chunks=4)
-    say("server: 60 queries, staggered arrivals, 4 chunks")
+    cfg = server.ServerConfig(chunks=chunks)
+    say(f"server: 60 queries, staggered arrivals, {chunks} chunks")
     with server.Server(t, 256 << 20, cfg) as srv:
         ids = []
         for i, (p, k) in enumerate(zip(pats, ks)):
@@ -71,7 +72,7 @@ def test_served_equals_alone_and_oracle(pm, served_text):
         st = srv.stats()
     say(f"  stats {st}")
     assert st["completed"] == len(pats) and st["failed"] == 0
-    assert st["steps"] >= 4
+    assert st["steps"] >= chunks and st["active"] == 0
     for i, (p, k) in enumerate(zip(pats, ks)):
         assert_same(res[i], alone(scan, t, p, k), f"query {i} m={len(p)} k={k} vs plain")
     # the oracle on the queries with few hits (all of them fit in seconds)
@@ -111,7 +112,8 @@ def test_served_under_memory_pressure(pm, served_text):
         assert_same(res[j], alone(scan, t, pats[i], ks[i]), f"pressure query {i}")
 
 
-def test_served_overflow_rescans(pm):
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_served_overflow_rescans(pm, chunks):
     """Queries whose hits far exceed the expected-hit estimate (many planted
     copies, some packed into one text stretch): the overflowed chunks are
     re-scanned and the results are still exact."""
@@ -129,7 +131,7 @@ def test_served_overflow_rescans(pm):
         p0 = 700_000 + 20 * j
         text[p0:p0 + 10] = np.frombuffer(b"ACGTTGCAAC", dtype=np.uint8)
     t = scan.encode_text(text)
-    cfg = server.ServerConfig(chunks=4)
+    cfg = server.ServerConfig(chunks=chunks)
     with server.Server(t, 128 << 20, cfg) as srv:
         ids = [srv.submit(p, k) for p, k in zip(pats, ks)]
         infos = [srv.wait(q, 60_000) for q in ids]
@@ -177,9 +179,11 @@ def test_served_timestamps_and_errors(pm):
         srv.drain(60_000)
 
 
-def test_served_large_results(pm):
-    """Results of a million hits and more are joined out of place by many
-    workgroups: still identical to the plain kernel alone."""
+@pytest.mark.parametrize("chunks", [1, 5])
+def test_served_large_results(pm, chunks):
+    """Results of a million hits and more: with several chunks they are
+    joined out of place by many workgroups, with one they stay where they
+    were scanned; either way identical to the plain kernel alone."""
     scan, server = pm
     from paper_1611_06115_amd import synth
 
@@ -187,7 +191,7 @@ def test_served_large_results(pm):
     t = scan.encode_text(text)
     pats = ["N" * 12, "NNRNNYNN", "ACGTMRWSYKVHDBNN", "GATTACA"]
     ks = [0, 1, 8, 3]
-    with server.Server(t, 512 << 20, server.ServerConfig(chunks=5)) as srv:
+    with server.Server(t, 512 << 20, server.ServerConfig(chunks=chunks)) as srv:
         ids = [srv.submit(p, k) for p, k in zip(pats, ks)]
         res = collect(srv, ids)
         st = srv.stats()
@@ -199,7 +203,7 @@ def test_served_large_results(pm):
 
 def test_served_genome_scale(pm):
     """The served workload at full size: the 3.1e9-base genome resident, the
-    engine configured as the benchmark runs it (8 chunks, 1024 slots, 64 GiB
+    engine configured as the benchmark runs it (one chunk, 1024 slots, 64 GiB
     arena), 240 seeded pool queries submitted in bursts while earlier ones
     are on the GPU.  Every result equals the plain kernel run alone (compared
     on the device), every planted copy is found, and for queries with few
