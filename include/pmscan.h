@@ -140,9 +140,11 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
  * over the whole text: ascending text positions and exact counts, the first
  * `capacity` hits in pos_dev / cnt_dev, *n_hits_dev = the total.  ws_dev:
  * 256-byte aligned, at least pm_scan_host_workspace_bytes(chunk_bases, m)
- * bytes.  A byte other than A/C/G/T gives PM_ERR_SYMBOL (the detail names
- * its index).  Returns when the scan is complete (it waits for both
- * streams); the host text must stay valid until then. */
+ * bytes (0 for an invalid chunk_bases or m).  chunk_bases: 1..2^48, else
+ * PM_ERR_ARG.  A byte other than A/C/G/T gives PM_ERR_SYMBOL (the detail
+ * names its index); with m > n there are no windows and the text is not
+ * read.  Returns when the scan is complete (it waits for both streams); the
+ * host text must stay valid until then. */
 uint64_t pm_scan_host_workspace_bytes(uint64_t chunk_bases, uint32_t m);
 pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* codes, uint32_t m,
                        uint32_t k, const void* image_dev, uint64_t chunk_bases, int64_t* pos_dev,

@@ -23,6 +23,10 @@ namespace {
 
 uint64_t align256(uint64_t x) { return (x + 255) / 256 * 256; }
 
+// Largest chunk accepted (2^48 windows, far beyond any device memory): keeps
+// every size and offset below free of 64-bit overflow.
+constexpr uint64_t kMaxChunkBases = 1ull << 48;
+
 // Workspace: two ASCII chunk buffers, two encoded chunk buffers, two
 // bad-symbol words, a hit total and one plain-scan workspace (the scans run
 // one after another on the compute stream).
@@ -79,7 +83,7 @@ struct BufferEvents {
 extern "C" {
 
 uint64_t pm_scan_host_workspace_bytes(uint64_t chunk_bases, uint32_t m) {
-    if (chunk_bases == 0 || m == 0) return 0;
+    if (chunk_bases == 0 || chunk_bases > kMaxChunkBases || m == 0) return 0;
     return host_layout(chunk_bases, m).bytes;
 }
 
@@ -92,7 +96,8 @@ pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* cod
         return set_error(PM_ERR_ARG, "null pointer");
     if (capacity > 0 && (!pos_dev || !cnt_dev)) return set_error(PM_ERR_ARG, "null output with capacity > 0");
     if (m == 0) return set_error(PM_ERR_ARG, "empty pattern (m = 0)");
-    if (chunk_bases == 0) return set_error(PM_ERR_ARG, "chunk_bases must be at least 1");
+    if (chunk_bases == 0 || chunk_bases > kMaxChunkBases)
+        return set_error(PM_ERR_ARG, "chunk_bases must be in 1..2^48");
     if (reinterpret_cast<uintptr_t>(ws_dev) % 256 != 0) return set_error(PM_ERR_ARG, "ws_dev must be 256-byte aligned");
     const HostScanLayout L = host_layout(chunk_bases, m);
     if (ws_bytes < L.bytes)
@@ -101,7 +106,7 @@ pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* cod
     hipStream_t cs = reinterpret_cast<hipStream_t>(copy_stream);
     uint8_t* ws = static_cast<uint8_t*>(ws_dev);
     const uint64_t nw = m <= n ? n - m + 1 : 0;
-    const uint64_t chunks = (nw + chunk_bases - 1) / chunk_bases;
+    const uint64_t chunks = nw / chunk_bases + (nw % chunk_bases != 0);
 
     BufferEvents ev;
     for (int b = 0; b < 2; ++b)
@@ -119,7 +124,7 @@ pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* cod
     };
     auto chunk_span = [&](uint64_t c, uint64_t& first, uint64_t& len) {
         first = c * chunk_bases;
-        len = std::min(n, first + chunk_bases + m - 1) - first;
+        len = std::min(n - first, chunk_bases + m - 1);
     };
     auto issue_copy = [&](uint64_t c) -> pm_status {
         const int b = (int)(c & 1);

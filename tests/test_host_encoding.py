@@ -130,6 +130,24 @@ def test_sizes():
     assert scan.lib().pm_pattern_bytes(33) == 32
 
 
+def test_host_scan_chunk_bounds():
+    """The host-memory scan's workspace grows with the chunk and is 0 for a
+    chunk outside 1..2^48 (whose sizes would overflow); such a chunk is
+    refused before any device work."""
+    ws = scan.scan_host_workspace_bytes
+    assert ws(0, 10) == 0 and ws(1000, 0) == 0
+    assert 0 < ws(1000, 10) < ws(10 ** 6, 10) < ws(1 << 48, 10)
+    assert ws((1 << 48) + 1, 10) == 0 and ws((1 << 64) - 1, 10) == 0
+    import ctypes
+
+    dummy = ctypes.c_void_p(256)  # never dereferenced: the argument check fails first
+    codes = scan.encode_pattern("ACGT")
+    for chunk in (0, (1 << 48) + 1, (1 << 64) - 1):
+        st = scan.lib().pm_scan_host(dummy, 10 ** 6, codes.ctypes.data, 4, 0, dummy, chunk, None, None, 0,
+                                     dummy, dummy, 1 << 30, None, None)
+        assert st == -1, chunk
+
+
 def test_expected_hits_closed_forms():
     """The output-sizing estimate: (n-m+1) * P(count <= k) for uniform bases,
     checked against closed forms (exact match probability prod |S_j|/4, and
