@@ -179,6 +179,31 @@ def test_served_timestamps_and_errors(pm):
         srv.drain(60_000)
 
 
+def test_served_more_chunks_than_windows(pm):
+    """4096 chunks over a 3000-base text: most chunk steps have no windows
+    for a query (or none at all); every result still equals the plain
+    kernel's and the oracle's."""
+    scan, server = pm
+    from paper_1611_06115_amd import synth
+
+    rnd = random.Random(90)
+    text = synth.iid_text(3000, seed=synth.SEED0 + 90, probs=GC41)
+    pats = ["ACGTNNAC", rand_pattern(rnd, 700, 0.2), "N" * 2999, "A" * 3001]
+    ks = [3, 470, 0, 0]
+    plant_copies(rnd, text, pats[0], 20, 1)
+    t = scan.encode_text(text)
+    with server.Server(t, 512 << 20, server.ServerConfig(chunks=4096)) as srv:
+        ids = [srv.submit(p, k) for p, k in zip(pats, ks)]
+        res = collect(srv, ids)
+        st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(pats) and st["active"] == 0
+    assert res[2][0].tolist() == [0, 1] and res[3][0].size == 0
+    for i, (p, k) in enumerate(zip(pats, ks)):
+        assert_same(res[i], alone(scan, t, p, k), f"query {i} vs plain")
+        assert_same(res[i], oracle_hits(text, p, k), f"query {i} vs oracle")
+
+
 @pytest.mark.parametrize("chunks", [1, 5])
 def test_served_large_results(pm, chunks):
     """Results of a million hits and more: with several chunks they are
