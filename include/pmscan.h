@@ -178,13 +178,15 @@ typedef struct {
 } pm_batch_config;
 
 /* Workspace bytes pm_scan_batch needs (depends on the patterns' lengths and
- * output capacities and on cfg, which may be NULL for the defaults). */
+ * output capacities and on cfg, which may be NULL for the defaults); 0 when
+ * the capacities sum to more than 2^44 hits. */
 uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m,
                                        const uint64_t* capacity, const pm_batch_config* cfg);
 
 /* Scan windows [win_begin, win_end) of the encoded text for `count` patterns.
  * Host inputs: codes (all patterns' Table 2 codes, concatenated), m[count],
- * k[count] (each <= 65535), out_off[count] and capacity[count]: pattern p's
+ * k[count] (each <= 65535), out_off[count] and capacity[count] (summing to
+ * at most 2^44, else PM_ERR_ARG): pattern p's
  * hits go to pos_dev/cnt_dev[out_off[p] .. out_off[p]+capacity[p]), in
  * ascending position order, with exact counts.  Device outputs per pattern:
  * n_hits_dev[p] = its total number of hits; status_dev[p] = 0 when its list

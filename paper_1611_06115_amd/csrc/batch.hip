@@ -427,6 +427,15 @@ BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capa
     return L;
 }
 
+bool capacities_fit(uint32_t count, const uint64_t* capacity) {
+    uint64_t left = kMaxTotalCapacity;
+    for (uint32_t p = 0; p < count; ++p) {
+        if (capacity[p] > left) return false;
+        left -= capacity[p];
+    }
+    return true;
+}
+
 pm_status check_batch_args(uint32_t count, const uint32_t* m, const uint32_t* k, const uint64_t* capacity) {
     if (count == 0) return PM_OK;
     if (!m || !k || !capacity) return set_error(PM_ERR_ARG, "null pointer");
@@ -434,6 +443,7 @@ pm_status check_batch_args(uint32_t count, const uint32_t* m, const uint32_t* k,
         if (m[p] == 0) return set_error(PM_ERR_ARG, "pattern " + std::to_string(p) + " is empty");
         if (k[p] > 65535) return set_error(PM_ERR_ARG, "k above 65535 for pattern " + std::to_string(p));
     }
+    if (!capacities_fit(count, capacity)) return set_error(PM_ERR_ARG, "output capacities above 2^44 hits in total");
     return PM_OK;
 }
 
@@ -457,6 +467,7 @@ uint32_t batch_auto_sub_ranges(uint32_t count, const pm_batch_config* cfg) {
 uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
                         const pm_batch_config* cfg, bool with_images) {
     if (count == 0 || !m || !capacity) return 256;
+    if (!capacities_fit(count, capacity)) return UINT64_MAX;
     const BatchShape sh = batch_shape(n, count, cfg, 0, n);
     return batch_layout(count, m, capacity, sh, with_images).bytes;
 }
@@ -464,6 +475,7 @@ uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uin
 uint64_t batch_desc_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
                           const pm_batch_config* cfg, bool with_images) {
     if (count == 0 || !m || !capacity) return 256;
+    if (!capacities_fit(count, capacity)) return UINT64_MAX;
     const BatchShape sh = batch_shape(n, count, cfg, 0, n);
     return batch_layout(count, m, capacity, sh, with_images).queue;
 }
@@ -686,7 +698,8 @@ pm_status pm_expected_hits(const uint8_t* codes, uint32_t m, uint32_t k, uint64_
 
 uint64_t pm_scan_batch_workspace_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
                                        const pm_batch_config* cfg) {
-    return batch_ws_bytes(n, count, m, capacity, cfg, true);
+    const uint64_t b = batch_ws_bytes(n, count, m, capacity, cfg, true);
+    return b == UINT64_MAX ? 0 : b;
 }
 
 pm_status pm_scan_batch(const void* text_dev, uint64_t n, uint32_t count, const uint8_t* codes,

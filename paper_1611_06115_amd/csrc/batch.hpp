@@ -56,8 +56,14 @@ constexpr uint64_t kAutoItems = 8ull * 256 * 16;
 // cfg->sub_ranges is 0.
 uint32_t batch_auto_sub_ranges(uint32_t count, const pm_batch_config* cfg);
 
+// Output capacities of one call may sum to at most kMaxTotalCapacity hits
+// (10 bytes each: far beyond any device), which keeps the workspace sizes
+// free of 64-bit overflow; larger ones are refused.
+constexpr uint64_t kMaxTotalCapacity = 1ull << 44;
+
 // Workspace bytes of a call over these patterns; with_images = false when
-// the caller keeps the images on the device.
+// the caller keeps the images on the device.  UINT64_MAX when the
+// capacities exceed kMaxTotalCapacity.
 uint64_t batch_ws_bytes(uint64_t n, uint32_t count, const uint32_t* m, const uint64_t* capacity,
                         const pm_batch_config* cfg, bool with_images);
 

@@ -167,3 +167,21 @@ def test_batch_workspace_grows_with_capacity():
     b2 = scan.Batch(["ACGT" * 10, "GATTACA"], [2, 1], 10 ** 6, capacities=[100000, 100])
     assert scan.batch_workspace_bytes(10 ** 6, b2) > scan.batch_workspace_bytes(10 ** 6, b1) > 0
     assert b2.out_off.tolist() == [0, 100000]
+
+
+def test_batch_capacities_are_bounded():
+    """Capacities summing past 2^44 hits (whose staging sizes would
+    overflow 64 bits) get workspace 0 and are refused before device work."""
+    import ctypes
+
+    pats, ks, n = ["ACGT" * 10, "GATTACA"], [2, 1], 10 ** 6
+    ok = scan.Batch(pats, ks, n, capacities=[1 << 43, 1 << 43])
+    assert scan.batch_workspace_bytes(n, ok) > 0
+    dummy = ctypes.c_void_p(256)  # never dereferenced: the argument check fails first
+    for caps in ([(1 << 44), 1], [(1 << 63), 0], [(1 << 64) - 1, (1 << 64) - 1]):
+        b = scan.Batch(pats, ks, n, capacities=caps)
+        assert scan.batch_workspace_bytes(n, b) == 0, caps
+        st = scan.lib().pm_scan_batch(dummy, n, len(b), b.codes.ctypes.data, b.m.ctypes.data, b.ks.ctypes.data,
+                                      b.out_off.ctypes.data, b.capacity.ctypes.data, 0, n, dummy, dummy, dummy,
+                                      dummy, dummy, 1 << 62, None, None)
+        assert st == -1, caps
