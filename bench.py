@@ -344,7 +344,11 @@ def run_mscale(args):
                                f"copies of m = 500 / 10000 / 100000 at the 5 sites per length of Tables 5-7, k={k}",
                    "per_m_ms": per_m,
                    "slowest_over_fastest": round(max(per_m.values()) / min(per_m.values()), 4),
-                   "rows": rows},
+                   "rows": rows,
+                   # context, not a target: the paper's mean CPU runtimes on the real
+                   # chromosome 2 (Sect. 3, Tables 5-7; its hardware is not stated)
+                   "paper_cpu_s": {"500": 6.595, "10000": 6.882, "100000": 6.980,
+                                   "slowest_over_fastest": 1.0584, "hardware": "not stated"}},
         # the count kernel over all runs: the text once per scan
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                      "frac": round(achieved / 8000.0, 4), "traffic": None},
