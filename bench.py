@@ -252,7 +252,12 @@ def run_plain(args):
                    "count_kernel_valu": None if valu_ops is None else {
                        "achieved": round(valu_ops / (kern_ms / 1e3) / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 1),
                        "unit": "T int32 VALU lane-ops/s",
-                       "frac": round(valu_ops / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)}},
+                       "frac": round(valu_ops / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)},
+                   # context, not a target: the paper's CPU rate, (n - m + 1) m logical
+                   # comparisons over its mean runtime for m = 500 on chromosome 2
+                   # (243 199 373 bases, 6.595 s; Sect. 3, Table 5; hardware not stated)
+                   "paper_cpu_context": {"value": round((243_199_373 - 499) * 500 / 6.595 / 1e9, 1),
+                                         "unit": "G comparisons/s", "hardware": "not stated"}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic},
