@@ -128,6 +128,38 @@ def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
     return step_ms, sum(a.elapsed_time(b) for a, b in pairs) / steps
 
 
+def time_steps_cold(fn, steps: int, warmup: int, stream, flush_bytes: int = 512 << 20):
+    """Like time_steps(kernel=True), but every step (timed on its own) comes
+    after a write of flush_bytes to a scratch buffer, larger than the
+    256 MB Infinity Cache, so that the text is read from HBM rather than from
+    a cache that still holds it from the previous step."""
+    import torch
+
+    from paper_1611_06115_amd import scan
+
+    scratch = torch.empty(flush_bytes, dtype=torch.uint8, device=stream.device)
+    for _ in range(warmup):
+        fn()
+    stream.synchronize()
+    step_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    kern_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in kern_ev:  # creates the events
+        a.record(stream)
+        b.record(stream)
+    stream.synchronize()
+    for i in range(steps):
+        scratch.fill_(i & 0xFF)
+        a, b = step_ev[i]
+        a.record(stream)
+        scan.time_next_scan(*kern_ev[i])
+        fn()
+        b.record(stream)
+    stream.synchronize()
+    del scratch
+    return (sum(a.elapsed_time(b) for a, b in step_ev) / steps,
+            sum(a.elapsed_time(b) for a, b in kern_ev) / steps)
+
+
 def host_cpu_model() -> str:
     """The host CPU's model name (first processor in /proc/cpuinfo)."""
     try:
@@ -211,7 +243,10 @@ def run_plain(args):
     m = pat.m
     ws = scan.Workspace(dev, text.n, capacity=1 << 20)
     step = lambda: scan.scan_async(text, pat, k, ws)  # noqa: E731
-    ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True)
+    if args.flush:
+        ms, kern_ms = time_steps_cold(step, args.steps, args.warmup, stream)
+    else:
+        ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True)
     hits = int(ws.n_hits.item())
     log(f"[bench] {args.steps} steps, {ms:.4f} ms/step (count kernel {kern_ms:.4f} ms), {hits} hits")
 
@@ -246,6 +281,8 @@ def run_plain(args):
         "dtype": "u32 bitwise (exact integer counts)",
         "data": "synthetic",
         "config": {"workload": desc, "n": text.n, "m": m, "k": k, "windows": nw, "hits": hits,
+                   "cache": ("cold: 512 MB written before each timed step" if args.flush
+                             else "warm: steps back to back"),
                    "windows_per_s": round(nw / sec, 1), "encode_kernel_ms": round(enc_ms, 4),
                    # the same kernel against the int32 VALU peak (its lane-ops
                    # per launch from the committed counter run)
@@ -718,6 +755,8 @@ def main():
     ap.add_argument("--slots", type=int, default=None, help="served: queries scanned together")
     ap.add_argument("--arena-gib", type=float, default=64.0, help="served: device memory of the server")
     ap.add_argument("--chunk", type=int, default=None, help="outofcore: windows per chunk")
+    ap.add_argument("--flush", action="store_true",
+                    help="genome/small/long_m: write 512 MB before each timed step (cold Infinity Cache)")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
