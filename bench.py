@@ -93,12 +93,13 @@ def valu_profile(workload: str):
     return t
 
 
-def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
+def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False, samples: list | None = None):
     """Mean ms per step over `steps` timed steps (HIP events on `stream`).
     With kernel=True also the mean duration of the scan's main kernel, from
     a pair of events the library records around that launch; those events
     go into a second timed loop of the same steps, so that they do not
-    perturb the step time."""
+    perturb the step time.  `samples`, if given, receives each step's kernel
+    duration (ms)."""
     import torch
 
     from paper_1611_06115_amd import scan
@@ -125,10 +126,13 @@ def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False):
         scan.time_next_scan(*pairs[i])
         fn()
     stream.synchronize()
-    return step_ms, sum(a.elapsed_time(b) for a, b in pairs) / steps
+    each = [a.elapsed_time(b) for a, b in pairs]
+    if samples is not None:
+        samples.extend(each)
+    return step_ms, sum(each) / steps
 
 
-def time_steps_cold(fn, steps: int, warmup: int, stream, flush_bytes: int = 512 << 20):
+def time_steps_cold(fn, steps: int, warmup: int, stream, flush_bytes: int = 512 << 20, samples: list | None = None):
     """Like time_steps(kernel=True), but every step (timed on its own) comes
     after a write of flush_bytes to a scratch buffer, larger than the
     256 MB Infinity Cache, so that the text is read from HBM rather than from
@@ -156,8 +160,10 @@ def time_steps_cold(fn, steps: int, warmup: int, stream, flush_bytes: int = 512 
         b.record(stream)
     stream.synchronize()
     del scratch
-    return (sum(a.elapsed_time(b) for a, b in step_ev) / steps,
-            sum(a.elapsed_time(b) for a, b in kern_ev) / steps)
+    each = [a.elapsed_time(b) for a, b in kern_ev]
+    if samples is not None:
+        samples.extend(each)
+    return sum(a.elapsed_time(b) for a, b in step_ev) / steps, sum(each) / steps
 
 
 def host_cpu_model() -> str:
@@ -243,10 +249,11 @@ def run_plain(args):
     m = pat.m
     ws = scan.Workspace(dev, text.n, capacity=1 << 20)
     step = lambda: scan.scan_async(text, pat, k, ws)  # noqa: E731
+    kern_each = []
     if args.flush:
-        ms, kern_ms = time_steps_cold(step, args.steps, args.warmup, stream)
+        ms, kern_ms = time_steps_cold(step, args.steps, args.warmup, stream, samples=kern_each)
     else:
-        ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True)
+        ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True, samples=kern_each)
     hits = int(ws.n_hits.item())
     log(f"[bench] {args.steps} steps, {ms:.4f} ms/step (count kernel {kern_ms:.4f} ms), {hits} hits")
 
@@ -283,6 +290,8 @@ def run_plain(args):
         "config": {"workload": desc, "n": text.n, "m": m, "k": k, "windows": nw, "hits": hits,
                    "cache": ("cold: 512 MB written before each timed step" if args.flush
                              else "warm: steps back to back"),
+                   "count_kernel_ms": {"mean": round(kern_ms, 5), "sd": round(float(np.std(kern_each)), 5),
+                                       "runs": len(kern_each)},
                    "windows_per_s": round(nw / sec, 1), "encode_kernel_ms": round(enc_ms, 4),
                    # the same kernel against the int32 VALU peak (its lane-ops
                    # per launch from the committed counter run)
