@@ -151,6 +151,23 @@ pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* cod
                        uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev, void* ws_dev,
                        uint64_t ws_bytes, void* stream, void* copy_stream);
 
+/* Mismatch counts of every window by the Linhart-Shamir route of Sect. 1.3
+ * (eqs. 1-3): the correlation of the CRT-coded pattern with the text, carried
+ * as its residues modulo four primes above m (the full value outgrows 64
+ * bits, Sect. 1.3.5) and computed with number-theoretic transforms over text
+ * blocks that overlap by m-1.  A second exact route beside pm_scan: it gives
+ * every window's count whatever k, at a cost that does not depend on k.
+ * text_dev: the encoded text (16-byte aligned); codes: m Table 2 codes (host;
+ * m in 1..2^22, larger is PM_ERR_UNSUPPORTED).  counts_dev receives
+ * counts_dev[i] = number of mismatches of window i, for i in [0, n-m+1)
+ * (nothing when m > n).  ws_dev: 256-byte aligned, at least
+ * pm_crt_counts_workspace_bytes(n, m) bytes (0 for an invalid m).  Returns
+ * once the pattern has been staged (one small synchronous copy); the rest
+ * runs asynchronously on `stream`. */
+uint64_t pm_crt_counts_workspace_bytes(uint64_t n, uint32_t m);
+pm_status pm_crt_counts(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m,
+                        uint32_t* counts_dev, void* ws_dev, uint64_t ws_bytes, void* stream);
+
 /* Measurement hook: the next pm_scan or pm_scan_batch call made by this
  * thread records ev_begin on its stream right before its main kernel launch
  * (the count kernel; the batched kernels) and ev_end right after it, so that

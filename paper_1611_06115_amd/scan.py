@@ -52,6 +52,8 @@ def lib():
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
                               i32),
             "pm_time_next_scan": ([vp, vp], i32),
+            "pm_crt_counts_workspace_bytes": ([u64, u32], u64),
+            "pm_crt_counts": ([vp, u64, vp, u32, vp, vp, u64, vp], i32),
             "pm_scan_host_workspace_bytes": ([u64, u32], u64),
             "pm_scan_host": ([vp, u64, vp, u32, u32, vp, u64, vp, vp, u64, vp, vp, u64, vp, vp], i32),
             "pm_server_now_ns": ([], u64),
@@ -225,6 +227,27 @@ def scan_async(text: Text, pattern: Pattern, k: int, ws: Workspace, win_begin: i
         ctypes.c_void_p(ws.pos.data_ptr()), ctypes.c_void_p(ws.cnt.data_ptr()), ws.capacity,
         ctypes.c_void_p(ws.n_hits.data_ptr()), ctypes.c_void_p(ws.ws.data_ptr()), ws.ws.numel(),
         _stream(stream)))
+
+
+def crt_counts_workspace_bytes(n: int, m: int) -> int:
+    return int(lib().pm_crt_counts_workspace_bytes(int(n), int(m)))
+
+
+def crt_counts(text: Text, pattern: Pattern | str, stream=None):
+    """Every window's mismatch count by the transform route (pm_crt_counts):
+    an int32 device tensor of n-m+1 counts (empty when m > n)."""
+    import torch
+
+    pattern = pattern if isinstance(pattern, Pattern) else Pattern(pattern)
+    dev = text.data.device
+    nw = text.n - pattern.m + 1 if pattern.m <= text.n else 0
+    out = torch.empty(max(nw, 0), dtype=torch.int32, device=dev)
+    ws = torch.empty(max(crt_counts_workspace_bytes(text.n, pattern.m), 256), dtype=torch.uint8, device=dev)
+    check(lib().pm_crt_counts(
+        ctypes.c_void_p(text.data.data_ptr()), text.n, pattern.codes.ctypes.data, pattern.m,
+        ctypes.c_void_p(out.data_ptr() if nw else 0), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        _stream(stream)))
+    return out
 
 
 def scan_host_workspace_bytes(chunk_bases: int, m: int) -> int:

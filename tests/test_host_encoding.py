@@ -169,6 +169,26 @@ def test_batch_workspace_grows_with_capacity():
     assert b2.out_off.tolist() == [0, 100000]
 
 
+def test_crt_route_workspace_and_arguments():
+    """The transform route's workspace: 0 for m = 0 or m above 2^22, grows
+    with the block (whose length is a power of two of at least 2m); bad
+    arguments are refused before device work."""
+    import ctypes
+
+    ws = scan.crt_counts_workspace_bytes
+    assert ws(1000, 0) == 0 and ws(10 ** 6, (1 << 22) + 1) == 0
+    assert 0 < ws(1000, 10) <= ws(10 ** 6, 10) <= ws(10 ** 9, 10) < ws(10 ** 9, 1 << 21)
+    assert ws(10 ** 9, 1 << 22) >= 40 * (1 << 23)
+    dummy = ctypes.c_void_p(256)  # never dereferenced: the argument check fails first
+    codes = scan.encode_pattern("ACGT")
+    assert scan.lib().pm_crt_counts(dummy, 100, codes.ctypes.data, 0, dummy, dummy, 1 << 30, None) == -1
+    assert scan.lib().pm_crt_counts(dummy, 100, codes.ctypes.data, (1 << 22) + 1, dummy, dummy, 1 << 30, None) == -5
+    bad = np.array([16, 1], dtype=np.uint8)
+    assert scan.lib().pm_crt_counts(dummy, 100, bad.ctypes.data, 2, dummy, dummy, 1 << 30, None) == -2
+    small = scan.lib().pm_crt_counts(dummy, 100, codes.ctypes.data, 4, dummy, dummy, 16, None)
+    assert small == -4
+
+
 def test_batch_capacities_are_bounded():
     """Capacities summing past 2^44 hits (whose staging sizes would
     overflow 64 bits) get workspace 0 and are refused before device work."""
