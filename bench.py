@@ -409,6 +409,96 @@ def run_mscale(args):
     return result
 
 
+def ls_direct_uint64_max_m(limit: int = 4000) -> int:
+    """Largest m for which the Linhart-Shamir correlation, computed directly
+    (no residues), stays below 2^64: m terms of n_S < M times the largest
+    text code M / k_1, with k_1 < ... < k_4 the four smallest primes above m
+    and M their product (the limit of Sect. 1.3.5)."""
+    def is_prime(x):
+        return x > 1 and all(x % d for d in range(2, int(x ** 0.5) + 1))
+
+    best = 0
+    for m in range(1, limit):
+        ks, x = [], m + 1
+        while len(ks) < 4:
+            if is_prime(x):
+                ks.append(x)
+            x += 1
+        big_m = ks[0] * ks[1] * ks[2] * ks[3]
+        if m * (big_m - 1) * (big_m // ks[0]) < 1 << 64:
+            best = m
+    return best
+
+
+def run_crt(args):
+    """The Linhart-Shamir transform route (pm_crt_counts, Sect. 1.3): every
+    window's mismatch count of one pattern over the long-pattern text, timed
+    beside the early-stop scan of the same pattern.  The counts at or below
+    k must equal the scan's hits."""
+    import numpy as np
+    import torch
+
+    from paper_1611_06115_amd import scan, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.long_m(n=args.n or 64_000_000)
+    pi = 1 if args.m == 4096 else 0
+    pattern, k = w.patterns[pi], args.k if args.k is not None else 16
+    stream = torch.cuda.current_stream()
+    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
+    stream.synchronize()
+    text.check()
+    pat = scan.Pattern(pattern)
+    m = pat.m
+    nw = text.n - m + 1
+    out = torch.empty(nw, dtype=torch.int32, device=dev)
+    ws = torch.empty(scan.crt_counts_workspace_bytes(text.n, m), dtype=torch.uint8, device=dev)
+    ms = time_steps(lambda: scan.crt_counts_into(text, pat, out, ws), args.steps, args.warmup, stream)
+    sws = scan.Workspace(dev, text.n, capacity=1 << 20)
+    scan_ms = time_steps(lambda: scan.scan_async(text, pat, k, sws), args.steps, args.warmup, stream)
+    sel = torch.nonzero(out <= k).flatten()
+    hits = int(sws.n_hits.item())
+    if not (sel.numel() == hits and torch.equal(sel, sws.pos[:hits])
+            and torch.equal(out[sel], sws.cnt[:hits].to(torch.int32))):
+        raise SystemExit("transform-route counts at or below k differ from the scan's hits")
+    log(f"[bench] crt route {ms:.3f} ms per pass over {text.n} bases (scan {scan_ms:.4f} ms), {hits} hits agree")
+    sec = ms / 1e3
+    algo_bytes = 0.25 * text.n + 4.0 * nw  # the text once and every window's count
+    result = {
+        "metric": "G base-pattern comparisons/sec",
+        "value": round(nw * m / sec / 1e9, 2),
+        "unit": "G comparisons/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 modular (exact integer counts)", "data": "synthetic",
+        "config": {"workload": f"crt: n={text.n} i.i.d. GC 0.41, m={m}, every window's count by the "
+                               f"Linhart-Shamir route (number-theoretic transforms, blocks of 2^20)",
+                   "windows": nw, "k_checked": k, "hits": hits, "scan_ms": round(scan_ms, 4),
+                   "ls_direct_uint64_max_m": ls_direct_uint64_max_m()},
+        # the route's own bytes are the text and the counts; its transforms
+        # pass each block's working set through the caches 2 log2(L) times
+        "roofline": {"bound": "hbm", "achieved": round(algo_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(algo_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+
+        sets = oracle.parse(pattern)
+        sample = 20_000
+        while True:
+            t0 = time.perf_counter()
+            oracle.counts(w.text[:sample + m - 1], sets)
+            dt = time.perf_counter() - t0
+            if dt >= 5.0 or sample >= nw:
+                break
+            sample = min(nw, sample * 4)
+        result["cpu_baseline"] = {"value": round(sample * m / dt / 1e9, 3), "unit": "G comparisons/s",
+                                  "cores": 1, "kind": "oracle", "cpu": host_cpu_model(),
+                                  "sample": f"full counts (no early stop) of windows [0, {sample}), {dt:.1f} s"}
+    return result
+
+
 def run_outofcore(args):
     """The genome workload with the text kept in pinned host memory and
     scanned by streaming it through the device in chunks with an m-1 overlap
@@ -751,7 +841,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale", "outofcore"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale", "outofcore", "crt"])
     ap.add_argument("--count", type=int, default=None, help="batched: number of patterns")
     ap.add_argument("--group", type=int, default=None, help="batched, served: patterns per text tile")
     ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
@@ -780,7 +870,7 @@ def main():
               "by text range with an m-1 overlap and no exchange, see the design notes", flush=True)
         raise SystemExit(2)
     run = {"batched": run_batched, "served": run_served, "mscale": run_mscale,
-           "outofcore": run_outofcore}.get(args.workload, run_plain)
+           "outofcore": run_outofcore, "crt": run_crt}.get(args.workload, run_plain)
     res = run(args)
     print(json.dumps(res), flush=True)
 

@@ -243,11 +243,17 @@ def crt_counts(text: Text, pattern: Pattern | str, stream=None):
     nw = text.n - pattern.m + 1 if pattern.m <= text.n else 0
     out = torch.empty(max(nw, 0), dtype=torch.int32, device=dev)
     ws = torch.empty(max(crt_counts_workspace_bytes(text.n, pattern.m), 256), dtype=torch.uint8, device=dev)
+    crt_counts_into(text, pattern, out, ws, stream)
+    return out
+
+
+def crt_counts_into(text: Text, pattern: Pattern, out, ws, stream=None) -> None:
+    """Enqueue one pm_crt_counts into caller-supplied tensors (out: n-m+1
+    int32 counts, ws: crt_counts_workspace_bytes bytes)."""
     check(lib().pm_crt_counts(
         ctypes.c_void_p(text.data.data_ptr()), text.n, pattern.codes.ctypes.data, pattern.m,
-        ctypes.c_void_p(out.data_ptr() if nw else 0), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+        ctypes.c_void_p(out.data_ptr() if out.numel() else 0), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
         _stream(stream)))
-    return out
 
 
 def scan_host_workspace_bytes(chunk_bases: int, m: int) -> int:
