@@ -68,6 +68,17 @@ def test_bench_mscale_and_outofcore_contract():
     assert r["cpu_baseline"]["kind"] == "oracle"
 
 
+def test_bench_crt_contract():
+    """The transform-route line (its counts at or below k are checked
+    against the scan's hits inside the bench)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "crt", "--n", "3000000", "--steps", "2", "--warmup", "1", "--no-cpu-baseline")
+    check_contract(r)
+    c = r["config"]
+    assert c["ls_direct_uint64_max_m"] == 240 and c["windows"] == 3_000_000 - 1024 + 1 and c["scan_ms"] > 0
+
+
 def test_time_next_scan_brackets_the_count_kernel():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
