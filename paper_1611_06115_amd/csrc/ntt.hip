@@ -44,10 +44,17 @@ namespace {
 constexpr uint32_t kP = 998244353u;  // 119 * 2^23 + 1
 constexpr uint32_t kRoot = 3;        // a primitive root modulo kP
 constexpr uint32_t kMaxLogL = 23;    // 2^23 divides kP - 1
-constexpr uint32_t kMinLogL = 10;
+constexpr uint32_t kMinLogL = 11;
 constexpr uint32_t kBlockLogL = 20;  // block length for long texts
 constexpr uint32_t kMaxM = 1u << (kMaxLogL - 1);
 constexpr unsigned kTPB = 256;
+// The innermost stages (butterflies within kLdsN consecutive elements) run in
+// LDS: one workgroup of kLdsN / 2 threads per chunk, one butterfly per thread
+// per stage, instead of one pass over the whole array per stage.
+constexpr uint32_t kLdsLog = 11;
+constexpr uint32_t kLdsN = 1u << kLdsLog;
+constexpr unsigned kLdsTPB = kLdsN / 2;
+static_assert(kMinLogL >= kLdsLog, "every block holds whole LDS chunks");
 
 __host__ __device__ inline uint32_t mul_mod(uint32_t a, uint32_t b) { return (uint32_t)((uint64_t)a * b % kP); }
 __device__ inline uint32_t add_mod(uint32_t a, uint32_t b) {
@@ -177,20 +184,67 @@ __global__ void output_kernel(const uint32_t* z, uint32_t m, uint64_t start, uin
         counts[start + i] = mul_mod(z[i + m - 1], inv_l);
 }
 
-// Forward transform (decimation in frequency) of `count` arrays of L.
+// The decimation-in-frequency stages len = kLdsN/2 .. 1 of one kLdsN chunk
+// (chunk blockIdx.x over the `count` arrays of L), in LDS.  Their butterfly
+// pairs never leave the chunk, since 2 len divides kLdsN.
+__global__ __launch_bounds__(kLdsTPB) void dif_tail_kernel(uint32_t* a, uint32_t L, const uint32_t* tw) {
+    __shared__ uint32_t sh[kLdsN];
+    const uint32_t per_array = L / kLdsN;
+    uint32_t* p = a + (uint64_t)(blockIdx.x / per_array) * L + (uint64_t)(blockIdx.x % per_array) * kLdsN;
+    const uint32_t t = threadIdx.x;
+    sh[t] = p[t];
+    sh[t + kLdsTPB] = p[t + kLdsTPB];
+    __syncthreads();
+    for (uint32_t len = kLdsN / 2; len >= 1; len >>= 1) {
+        const uint32_t j = t % len, i = (t / len) * 2 * len + j;
+        const uint32_t u = sh[i], v = sh[i + len];
+        sh[i] = add_mod(u, v);
+        sh[i + len] = mul_mod(sub_mod(u, v), tw[j * (L / (2 * len))]);
+        __syncthreads();
+    }
+    p[t] = sh[t];
+    p[t + kLdsTPB] = sh[t + kLdsTPB];
+}
+
+// The decimation-in-time stages len = 1 .. kLdsN/2 of one kLdsN chunk of the
+// one array of L, in LDS.
+__global__ __launch_bounds__(kLdsTPB) void dit_head_kernel(uint32_t* a, uint32_t L, const uint32_t* itw) {
+    __shared__ uint32_t sh[kLdsN];
+    uint32_t* p = a + (uint64_t)blockIdx.x * kLdsN;
+    const uint32_t t = threadIdx.x;
+    sh[t] = p[t];
+    sh[t + kLdsTPB] = p[t + kLdsTPB];
+    __syncthreads();
+    for (uint32_t len = 1; len <= kLdsN / 2; len <<= 1) {
+        const uint32_t j = t % len, i = (t / len) * 2 * len + j;
+        const uint32_t u = sh[i], v = mul_mod(sh[i + len], itw[j * (L / (2 * len))]);
+        sh[i] = add_mod(u, v);
+        sh[i + len] = sub_mod(u, v);
+        __syncthreads();
+    }
+    p[t] = sh[t];
+    p[t + kLdsTPB] = sh[t + kLdsTPB];
+}
+
+// Forward transform (decimation in frequency) of `count` arrays of L: the
+// stages with len >= kLdsN one pass each, then the rest in LDS.
 hipError_t forward(uint32_t* a, uint32_t logL, uint32_t count, const uint32_t* tw, hipStream_t s) {
     const uint32_t L = 1u << logL;
-    for (uint32_t len = L / 2; len >= 1; len /= 2) {
+    for (uint32_t len = L / 2; len >= kLdsN; len /= 2) {
         dif_stage_kernel<<<grid_for((uint64_t)(L / 2) * count), kTPB, 0, s>>>(a, L, len, L / (2 * len), tw, count);
         if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
-    return hipSuccess;
+    dif_tail_kernel<<<(L / kLdsN) * count, kLdsTPB, 0, s>>>(a, L, tw);
+    return hipGetLastError();
 }
 
-// Inverse transform (decimation in time) of one array of L, without the 1/L.
+// Inverse transform (decimation in time) of one array of L, without the 1/L:
+// the stages with len < kLdsN in LDS, then the rest one pass each.
 hipError_t inverse(uint32_t* a, uint32_t logL, const uint32_t* itw, hipStream_t s) {
     const uint32_t L = 1u << logL;
-    for (uint32_t len = 1; len <= L / 2; len *= 2) {
+    dit_head_kernel<<<L / kLdsN, kLdsTPB, 0, s>>>(a, L, itw);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    for (uint32_t len = kLdsN; len <= L / 2; len *= 2) {
         dit_stage_kernel<<<grid_for(L / 2), kTPB, 0, s>>>(a, L, len, L / (2 * len), itw);
         if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
