@@ -155,6 +155,45 @@ __global__ void dif_stage_kernel(uint32_t* a, uint32_t L, uint32_t len, uint32_t
     }
 }
 
+// Two decimation-in-frequency stages at once (half-sizes H and H/2) over
+// `count` arrays of L: each thread takes the four elements j, j+H/2, j+H,
+// j+3H/2 of its 2H block through both stages (one pass instead of two).
+__global__ void dif4_stage_kernel(uint32_t* a, uint32_t L, uint32_t H, const uint32_t* tw, uint32_t count) {
+    const uint32_t quarter = L / 4, Q = H / 2, sh = L / (2 * H), sq = L / H;
+    const uint64_t total = (uint64_t)quarter * count;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t arr = (uint32_t)(t / quarter), q = (uint32_t)(t % quarter);
+        const uint32_t j = q % Q, s = (q / Q) * 2 * H;
+        uint32_t* p = a + (uint64_t)arr * L + s + j;
+        const uint32_t a0 = p[0], a1 = p[Q], a2 = p[H], a3 = p[H + Q];
+        const uint32_t b0 = add_mod(a0, a2), b2 = mul_mod(sub_mod(a0, a2), tw[j * sh]);
+        const uint32_t b1 = add_mod(a1, a3), b3 = mul_mod(sub_mod(a1, a3), tw[(j + Q) * sh]);
+        const uint32_t w = tw[j * sq];
+        p[0] = add_mod(b0, b1);
+        p[Q] = mul_mod(sub_mod(b0, b1), w);
+        p[H] = add_mod(b2, b3);
+        p[H + Q] = mul_mod(sub_mod(b2, b3), w);
+    }
+}
+
+// Two decimation-in-time stages at once (half-sizes Q and 2Q) of the one
+// array of L, the mirror of dif4_stage_kernel.
+__global__ void dit4_stage_kernel(uint32_t* a, uint32_t L, uint32_t Q, const uint32_t* itw) {
+    const uint32_t quarter = L / 4, H = 2 * Q;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < quarter; q += gridDim.x * blockDim.x) {
+        const uint32_t j = q % Q, s = (q / Q) * 2 * H;
+        uint32_t* p = a + s + j;
+        const uint32_t w1 = itw[j * (L / (2 * Q))];
+        const uint32_t a0 = p[0], t1 = mul_mod(p[Q], w1), a2 = p[H], t3 = mul_mod(p[H + Q], w1);
+        const uint32_t b0 = add_mod(a0, t1), b1 = sub_mod(a0, t1), b2 = add_mod(a2, t3), b3 = sub_mod(a2, t3);
+        const uint32_t u2 = mul_mod(b2, itw[j * (L / (2 * H))]), u3 = mul_mod(b3, itw[(j + Q) * (L / (2 * H))]);
+        p[0] = add_mod(b0, u2);
+        p[H] = sub_mod(b0, u2);
+        p[Q] = add_mod(b1, u3);
+        p[H + Q] = sub_mod(b1, u3);
+    }
+}
+
 // One decimation-in-time stage of the inverse transform (one array of L).
 __global__ void dit_stage_kernel(uint32_t* a, uint32_t L, uint32_t len, uint32_t step, const uint32_t* itw) {
     const uint32_t half = L / 2;
@@ -230,8 +269,14 @@ __global__ __launch_bounds__(kLdsTPB) void dit_head_kernel(uint32_t* a, uint32_t
 // stages with len >= kLdsN one pass each, then the rest in LDS.
 hipError_t forward(uint32_t* a, uint32_t logL, uint32_t count, const uint32_t* tw, hipStream_t s) {
     const uint32_t L = 1u << logL;
-    for (uint32_t len = L / 2; len >= kLdsN; len /= 2) {
-        dif_stage_kernel<<<grid_for((uint64_t)(L / 2) * count), kTPB, 0, s>>>(a, L, len, L / (2 * len), tw, count);
+    for (uint32_t len = L / 2; len >= kLdsN;) {
+        if (len / 2 >= kLdsN) {  // two stages in one pass
+            dif4_stage_kernel<<<grid_for((uint64_t)(L / 4) * count), kTPB, 0, s>>>(a, L, len, tw, count);
+            len /= 4;
+        } else {
+            dif_stage_kernel<<<grid_for((uint64_t)(L / 2) * count), kTPB, 0, s>>>(a, L, len, L / (2 * len), tw, count);
+            len /= 2;
+        }
         if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
     dif_tail_kernel<<<(L / kLdsN) * count, kLdsTPB, 0, s>>>(a, L, tw);
@@ -244,8 +289,14 @@ hipError_t inverse(uint32_t* a, uint32_t logL, const uint32_t* itw, hipStream_t 
     const uint32_t L = 1u << logL;
     dit_head_kernel<<<L / kLdsN, kLdsTPB, 0, s>>>(a, L, itw);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
-    for (uint32_t len = kLdsN; len <= L / 2; len *= 2) {
-        dit_stage_kernel<<<grid_for(L / 2), kTPB, 0, s>>>(a, L, len, L / (2 * len), itw);
+    for (uint32_t len = kLdsN; len <= L / 2;) {
+        if (2 * len <= L / 2) {  // two stages in one pass
+            dit4_stage_kernel<<<grid_for(L / 4), kTPB, 0, s>>>(a, L, len, itw);
+            len *= 4;
+        } else {
+            dit_stage_kernel<<<grid_for(L / 2), kTPB, 0, s>>>(a, L, len, L / (2 * len), itw);
+            len *= 2;
+        }
         if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     }
     return hipSuccess;
