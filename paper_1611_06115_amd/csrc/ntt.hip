@@ -49,11 +49,12 @@ constexpr uint32_t kBlockLogL = 20;  // block length for long texts
 constexpr uint32_t kMaxM = 1u << (kMaxLogL - 1);
 constexpr unsigned kTPB = 256;
 // The innermost stages (butterflies within kLdsN consecutive elements) run in
-// LDS: one workgroup of kLdsN / 2 threads per chunk, one butterfly per thread
-// per stage, instead of one pass over the whole array per stage.
+// LDS: one workgroup of kLdsN / 4 threads per chunk, four elements per
+// thread, instead of one pass over the whole array per stage.
 constexpr uint32_t kLdsLog = 11;
 constexpr uint32_t kLdsN = 1u << kLdsLog;
-constexpr unsigned kLdsTPB = kLdsN / 2;
+constexpr unsigned kLdsTPB = kLdsN / 4;
+static_assert(kLdsLog % 2 == 1, "the LDS stages are pairs and one single stage");
 static_assert(kMinLogL >= kLdsLog, "every block holds whole LDS chunks");
 
 __host__ __device__ inline uint32_t mul_mod(uint32_t a, uint32_t b) { return (uint32_t)((uint64_t)a * b % kP); }
@@ -225,44 +226,73 @@ __global__ void output_kernel(const uint32_t* z, uint32_t m, uint64_t start, uin
 
 // The decimation-in-frequency stages len = kLdsN/2 .. 1 of one kLdsN chunk
 // (chunk blockIdx.x over the `count` arrays of L), in LDS.  Their butterfly
-// pairs never leave the chunk, since 2 len divides kLdsN.
+// pairs never leave the chunk, since 2 len divides kLdsN.  Each thread holds
+// four elements and takes them through two stages per barrier; the odd last
+// stage (len = 1, twiddle 1) takes two pairs per thread.
 __global__ __launch_bounds__(kLdsTPB) void dif_tail_kernel(uint32_t* a, uint32_t L, const uint32_t* tw) {
     __shared__ uint32_t sh[kLdsN];
     const uint32_t per_array = L / kLdsN;
     uint32_t* p = a + (uint64_t)(blockIdx.x / per_array) * L + (uint64_t)(blockIdx.x % per_array) * kLdsN;
     const uint32_t t = threadIdx.x;
-    sh[t] = p[t];
-    sh[t + kLdsTPB] = p[t + kLdsTPB];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) sh[t + r * kLdsTPB] = p[t + r * kLdsTPB];
     __syncthreads();
-    for (uint32_t len = kLdsN / 2; len >= 1; len >>= 1) {
-        const uint32_t j = t % len, i = (t / len) * 2 * len + j;
-        const uint32_t u = sh[i], v = sh[i + len];
-        sh[i] = add_mod(u, v);
-        sh[i + len] = mul_mod(sub_mod(u, v), tw[j * (L / (2 * len))]);
+    for (uint32_t H = kLdsN / 2; H >= 2; H /= 4) {
+        const uint32_t Q = H / 2, j = t % Q, i = (t / Q) * 2 * H + j;
+        const uint32_t a0 = sh[i], a1 = sh[i + Q], a2 = sh[i + H], a3 = sh[i + H + Q];
+        const uint32_t b0 = add_mod(a0, a2), b2 = mul_mod(sub_mod(a0, a2), tw[j * (L / (2 * H))]);
+        const uint32_t b1 = add_mod(a1, a3), b3 = mul_mod(sub_mod(a1, a3), tw[(j + Q) * (L / (2 * H))]);
+        const uint32_t w = tw[j * (L / H)];
+        sh[i] = add_mod(b0, b1);
+        sh[i + Q] = mul_mod(sub_mod(b0, b1), w);
+        sh[i + H] = add_mod(b2, b3);
+        sh[i + H + Q] = mul_mod(sub_mod(b2, b3), w);
         __syncthreads();
     }
-    p[t] = sh[t];
-    p[t + kLdsTPB] = sh[t + kLdsTPB];
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+        const uint32_t e = t + r * kLdsTPB;
+        const uint32_t u = sh[2 * e], v = sh[2 * e + 1];
+        sh[2 * e] = add_mod(u, v);
+        sh[2 * e + 1] = sub_mod(u, v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) p[t + r * kLdsTPB] = sh[t + r * kLdsTPB];
 }
 
 // The decimation-in-time stages len = 1 .. kLdsN/2 of one kLdsN chunk of the
-// one array of L, in LDS.
+// one array of L, in LDS: the odd first stage (len = 1, twiddle 1), then two
+// stages per barrier.
 __global__ __launch_bounds__(kLdsTPB) void dit_head_kernel(uint32_t* a, uint32_t L, const uint32_t* itw) {
     __shared__ uint32_t sh[kLdsN];
     uint32_t* p = a + (uint64_t)blockIdx.x * kLdsN;
     const uint32_t t = threadIdx.x;
-    sh[t] = p[t];
-    sh[t + kLdsTPB] = p[t + kLdsTPB];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) sh[t + r * kLdsTPB] = p[t + r * kLdsTPB];
     __syncthreads();
-    for (uint32_t len = 1; len <= kLdsN / 2; len <<= 1) {
-        const uint32_t j = t % len, i = (t / len) * 2 * len + j;
-        const uint32_t u = sh[i], v = mul_mod(sh[i + len], itw[j * (L / (2 * len))]);
-        sh[i] = add_mod(u, v);
-        sh[i + len] = sub_mod(u, v);
+#pragma unroll
+    for (uint32_t r = 0; r < 2; ++r) {
+        const uint32_t e = t + r * kLdsTPB;
+        const uint32_t u = sh[2 * e], v = sh[2 * e + 1];
+        sh[2 * e] = add_mod(u, v);
+        sh[2 * e + 1] = sub_mod(u, v);
+    }
+    __syncthreads();
+    for (uint32_t Q = 2; Q <= kLdsN / 4; Q *= 4) {
+        const uint32_t H = 2 * Q, j = t % Q, i = (t / Q) * 2 * H + j;
+        const uint32_t w1 = itw[j * (L / (2 * Q))];
+        const uint32_t a0 = sh[i], t1 = mul_mod(sh[i + Q], w1), a2 = sh[i + H], t3 = mul_mod(sh[i + H + Q], w1);
+        const uint32_t b0 = add_mod(a0, t1), b1 = sub_mod(a0, t1), b2 = add_mod(a2, t3), b3 = sub_mod(a2, t3);
+        const uint32_t u2 = mul_mod(b2, itw[j * (L / (2 * H))]), u3 = mul_mod(b3, itw[(j + Q) * (L / (2 * H))]);
+        sh[i] = add_mod(b0, u2);
+        sh[i + H] = sub_mod(b0, u2);
+        sh[i + Q] = add_mod(b1, u3);
+        sh[i + H + Q] = sub_mod(b1, u3);
         __syncthreads();
     }
-    p[t] = sh[t];
-    p[t + kLdsTPB] = sh[t + kLdsTPB];
+#pragma unroll
+    for (uint32_t r = 0; r < 4; ++r) p[t + r * kLdsTPB] = sh[t + r * kLdsTPB];
 }
 
 // Forward transform (decimation in frequency) of `count` arrays of L: the
