@@ -195,6 +195,65 @@ __global__ void dit4_stage_kernel(uint32_t* a, uint32_t L, uint32_t Q, const uin
     }
 }
 
+// Three decimation-in-frequency stages at once (half-sizes H, H/2, H/4)
+// over `count` arrays of L: each thread takes the eight elements j + r H/4
+// (r < 8) of its 2H block through all three.  At stage k the pairs are r and
+// r + d with d = 4 >> k; the pair's index within its 2h block (h = d H/4) is
+// (r mod d) H/4 + j.
+__global__ void dif8_stage_kernel(uint32_t* a, uint32_t L, uint32_t H, const uint32_t* tw, uint32_t count) {
+    const uint32_t eighth = L / 8, Q4 = H / 4;
+    const uint64_t total = (uint64_t)eighth * count;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total; t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t arr = (uint32_t)(t / eighth), q = (uint32_t)(t % eighth);
+        const uint32_t j = q % Q4, s = (q / Q4) * 2 * H;
+        uint32_t* p = a + (uint64_t)arr * L + s + j;
+        uint32_t e[8];
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) e[r] = p[r * Q4];
+#pragma unroll
+        for (uint32_t k = 0; k < 3; ++k) {
+            const uint32_t d = 4u >> k, step = L / (2 * Q4 * d);
+#pragma unroll
+            for (uint32_t r = 0; r < 8; ++r) {
+                if ((r / d) % 2 == 0) {
+                    const uint32_t u = e[r], v = e[r + d];
+                    e[r] = add_mod(u, v);
+                    e[r + d] = mul_mod(sub_mod(u, v), tw[((r % d) * Q4 + j) * step]);
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) p[r * Q4] = e[r];
+    }
+}
+
+// Three decimation-in-time stages at once (half-sizes Q, 2Q, 4Q) of the one
+// array of L, the mirror of dif8_stage_kernel.
+__global__ void dit8_stage_kernel(uint32_t* a, uint32_t L, uint32_t Q, const uint32_t* itw) {
+    const uint32_t eighth = L / 8, H = 4 * Q;
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < eighth; q += gridDim.x * blockDim.x) {
+        const uint32_t j = q % Q, s = (q / Q) * 2 * H;
+        uint32_t* p = a + s + j;
+        uint32_t e[8];
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) e[r] = p[r * Q];
+#pragma unroll
+        for (uint32_t k = 3; k-- > 0;) {
+            const uint32_t d = 4u >> k, step = L / (2 * Q * d);
+#pragma unroll
+            for (uint32_t r = 0; r < 8; ++r) {
+                if ((r / d) % 2 == 0) {
+                    const uint32_t u = e[r], v = mul_mod(e[r + d], itw[((r % d) * Q + j) * step]);
+                    e[r] = add_mod(u, v);
+                    e[r + d] = sub_mod(u, v);
+                }
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < 8; ++r) p[r * Q] = e[r];
+    }
+}
+
 // One decimation-in-time stage of the inverse transform (one array of L).
 __global__ void dit_stage_kernel(uint32_t* a, uint32_t L, uint32_t len, uint32_t step, const uint32_t* itw) {
     const uint32_t half = L / 2;
@@ -300,7 +359,10 @@ __global__ __launch_bounds__(kLdsTPB) void dit_head_kernel(uint32_t* a, uint32_t
 hipError_t forward(uint32_t* a, uint32_t logL, uint32_t count, const uint32_t* tw, hipStream_t s) {
     const uint32_t L = 1u << logL;
     for (uint32_t len = L / 2; len >= kLdsN;) {
-        if (len / 2 >= kLdsN) {  // two stages in one pass
+        if (len / 4 >= kLdsN) {  // three stages in one pass
+            dif8_stage_kernel<<<grid_for((uint64_t)(L / 8) * count), kTPB, 0, s>>>(a, L, len, tw, count);
+            len /= 8;
+        } else if (len / 2 >= kLdsN) {  // two stages in one pass
             dif4_stage_kernel<<<grid_for((uint64_t)(L / 4) * count), kTPB, 0, s>>>(a, L, len, tw, count);
             len /= 4;
         } else {
@@ -320,7 +382,10 @@ hipError_t inverse(uint32_t* a, uint32_t logL, const uint32_t* itw, hipStream_t 
     dit_head_kernel<<<L / kLdsN, kLdsTPB, 0, s>>>(a, L, itw);
     if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
     for (uint32_t len = kLdsN; len <= L / 2;) {
-        if (2 * len <= L / 2) {  // two stages in one pass
+        if (4 * len <= L / 2) {  // three stages in one pass
+            dit8_stage_kernel<<<grid_for(L / 8), kTPB, 0, s>>>(a, L, len, itw);
+            len *= 8;
+        } else if (2 * len <= L / 2) {  // two stages in one pass
             dit4_stage_kernel<<<grid_for(L / 4), kTPB, 0, s>>>(a, L, len, itw);
             len *= 4;
         } else {
