@@ -33,13 +33,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-VALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # int32 VALU lane-ops/s: CUs x lanes per clock x clock
+# nominal int32 VALU lane-ops/s: CUs x lanes per clock (two instructions
+# issued per SIMD per 4-clock cycle) x clock; used only when no calibration
+# run has been committed
+VALU_NOMINAL_TOPS = 256 * 128 * 2.4e9 / 1e12
+
+
+def valu_peak() -> dict:
+    """The VALU ceilings measured on the box by bench.py --valu-calibration
+    (committed as profiles/valu_calibration.json): "peak" is the highest
+    issue rate measured for any instruction (independent chains, full
+    occupancy), "mix" the rate of the filter's 1:2 mix of alignbit and
+    three-input LUT operations.  Falls back to the nominal figure."""
+    path = os.path.join(PROFILE_DIR, "valu_calibration.json")
+    if os.path.exists(path):
+        with open(path) as f:
+            c = json.load(f)["ceilings_T"]
+        return {"peak": c["full_rate_max"], "mix": c["filter_mix_1_alignbit_2_bitop3"],
+                "alignbit": c["v_alignbit_b32"], "source": "profiles/valu_calibration.json"}
+    return {"peak": round(VALU_NOMINAL_TOPS, 1), "mix": None, "alignbit": None, "source": "nominal"}
 
 
 # The sources that define each workload's kernels: a committed counter run
 # applies only while these are unchanged.
 KERNEL_SOURCES = {
-    "genome": ("pmscan.hip", "plan.cpp", "plan.hpp", "scan_core.hpp"),
+    "genome": ("scan_kernels.hpp", "plan.cpp", "plan.hpp", "scan_core.hpp"),
     "batched": ("batch.hip", "batch.hpp", "plan.cpp", "plan.hpp", "scan_core.hpp"),
 }
 
@@ -178,30 +196,43 @@ def host_cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0):
-    """The oracle (plain brute force with early stop, all host threads up to
-    16) on a prefix of the windows, sized to about target_s seconds."""
+def host_threads() -> int:
+    """Threads the oracle baseline uses: every core this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def cpu_baseline(text, pattern: str, k: int, m: int, target_s: float = 10.0, lists: bool = False):
+    """The oracle (plain brute force with early stop, on every core the
+    process may use) on a prefix of the windows, sized to about target_s
+    seconds.  With lists=True also returns the oracle's (positions, counts)
+    for that prefix and its end."""
     import oracle
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     sets = oracle.parse(pattern)
     nw = text.size - m + 1
     sample = min(nw, 5_000_000)
     while True:  # grow the sample until one run takes about target_s
         t0 = time.perf_counter()
-        _, _, hits = oracle.scan(text, sets, k, threads=threads, win_end=sample, capacity=1 << 16)
+        pos, cnt, hits = oracle.scan(text, sets, k, threads=threads, win_end=sample, capacity=1 << 20)
         dt = time.perf_counter() - t0
         if dt >= 0.6 * target_s or sample >= nw:
             break
         sample = int(min(nw, sample * min(8.0, max(1.5, target_s / max(dt, 1e-3)))))
-    return {
+    res = {
         "value": round(sample * m / dt / 1e9, 3),
         "unit": "G comparisons/s",
-        "cores": threads,
+        "cores": threads, "cpu_count": os.cpu_count(),
         "kind": "oracle", "cpu": host_cpu_model(),
         "sample": f"windows [0, {sample}) of the same text ({sample / nw:.1%} of the pass), "
                   f"k={k}, {dt:.1f} s wall, {hits} hits",
     }
+    if lists:
+        return res, (pos, cnt, hits, sample)
+    return res
 
 
 def run_plain(args):
@@ -296,9 +327,10 @@ def run_plain(args):
                    # the same kernel against the int32 VALU peak (its lane-ops
                    # per launch from the committed counter run)
                    "count_kernel_valu": None if valu_ops is None else {
-                       "achieved": round(valu_ops / (kern_ms / 1e3) / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 1),
+                       "achieved": round(valu_ops / (kern_ms / 1e3) / 1e12, 2), "peak": valu_peak()["peak"],
                        "unit": "T int32 VALU lane-ops/s",
-                       "frac": round(valu_ops / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4)},
+                       "frac": round(valu_ops / (kern_ms / 1e3) / 1e12 / valu_peak()["peak"], 4),
+                       "mix_ceiling": valu_peak()["mix"], "peak_source": valu_peak()["source"]},
                    # context, not a target: the paper's CPU rate, (n - m + 1) m logical
                    # comparisons over its mean runtime for m = 500 on chromosome 2
                    # (243 199 373 bases, 6.595 s; Sect. 3, Table 5; hardware not stated)
@@ -310,7 +342,34 @@ def run_plain(args):
     }
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(w.text, pattern, k, m)
+        result["cpu_baseline"], (opos, ocnt, ohits, osample) = cpu_baseline(w.text, pattern, k, m, lists=True)
+        # the GPU list over the oracle's windows must equal the oracle's, hit for hit
+        gpos = ws.pos[:min(hits, ws.capacity)].cpu().numpy()
+        gcnt = ws.cnt[:min(hits, ws.capacity)].cpu().numpy()
+        sel = gpos < osample
+        if hits > ws.capacity or ohits != int(sel.sum()) or not (
+                np.array_equal(gpos[sel], opos) and np.array_equal(gcnt[sel], ocnt)):
+            raise SystemExit(f"GPU hits differ from the oracle's over windows [0, {osample})")
+        result["config"]["oracle_check"] = (f"the GPU list equals the oracle's over windows [0, {osample}) "
+                                            f"({osample / nw:.1%} of the pass, {ohits} hits)")
+        log(f"[bench] GPU list equals the oracle's over [0, {osample})")
+    if args.workload == "genome" and not args.no_served:
+        # the served form on the same resident text: Poisson arrivals at
+        # 1000 queries/s for 3 s from the served workload's query pool
+        from paper_1611_06115_amd import server
+
+        log("[bench] served latency on the resident text (1000 queries/s, 3 s)")
+        pats, kq = synth.query_pool(count=4000)
+        res = serve(text, [scan.Pattern(x) for x in pats], kq, 1000.0, 3.0,
+                    server.ServerConfig(chunks=0, max_active=0, batch=scan.BatchConfig(0, 0, 0, 0)), 64.0)
+        result["latency_ms"] = res["latency_ms"]
+        result["config"]["served"] = {"workload": "served form on this text: Poisson arrivals at 1000/s for 3 s "
+                                                  "from the served query pool (m log-uniform 20..5000, "
+                                                  "k ~ U{0..10}, class density ~ U[0,0.3]), not planted",
+                                      "queries": res["queries"], "qps_achieved": res["qps_achieved"],
+                                      "hits": res["hits"], "queue_ms": res["queue_ms"],
+                                      "value": res["value"], "unit": "G comparisons/s",
+                                      "checked": res["checked"]}
     return result
 
 
@@ -326,6 +385,62 @@ def copy_calibration(gib: float = 1.0, reps: int = 3):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
+def valu_calibration(target_ms: float = 3.0):
+    """Issue rates of the VALU instructions the scan kernels use, measured by
+    the probe library (csrc/calib.hip): lane-operations per second of
+    independent chains of one instruction (or the filter's 1:2 mix of
+    alignbit and three-input LUT operations) at 1-8 waves per SIMD.  Prints
+    one JSON object; the ceilings it reports are what the "alu" rooflines
+    are set against."""
+    import ctypes
+
+    from paper_1611_06115_amd import _build
+
+    if not os.path.exists(_build.CALIB_LIB):
+        raise SystemExit(f"{_build.CALIB_LIB} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(_build.CALIB_LIB)
+    L.pmc_kind_name.restype = ctypes.c_char_p
+    L.pmc_valu_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, ctypes.c_int,
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    cus = L.pmc_compute_units()
+
+    def probe(kind, chains, waves):
+        ms, ops = ctypes.c_double(), ctypes.c_double()
+        iters = 256
+        for _ in range(2):  # size the loop to about target_ms per launch
+            rc = L.pmc_valu_probe(kind, chains, waves, iters, 1, ctypes.byref(ms), ctypes.byref(ops))
+            if rc:
+                raise SystemExit(f"probe {kind} failed: hip error {rc}")
+            iters = max(64, int(iters * target_ms / max(ms.value, 1e-3)))
+        rc = L.pmc_valu_probe(kind, chains, waves, iters, 3, ctypes.byref(ms), ctypes.byref(ops))
+        if rc:
+            raise SystemExit(f"probe {kind} failed: hip error {rc}")
+        return ops.value / (ms.value / 1e3) / 1e12
+
+    rows = []
+    for kind in range(L.pmc_kind_count()):
+        name = L.pmc_kind_name(kind).decode()
+        waves_list = (1, 2, 4, 5, 8) if kind in (0, 1, 3, 8) else (4, 8)
+        for waves in waves_list:
+            for chains in ((1, 2, 4, 8) if kind in (0, 1, 8) and waves in (4, 5) else (8,)):
+                t = probe(kind, chains, waves)
+                rows.append({"kind": name, "waves_per_simd": waves, "chains": chains, "T_lane_ops_s": round(t, 2)})
+                log(f"[valu] {name:32s} waves {waves} chains {chains}: {t:6.2f} T lane-ops/s")
+    best = lambda name: max(r["T_lane_ops_s"] for r in rows if r["kind"] == name)  # noqa: E731
+    out = {
+        "compute_units": cus,
+        "nominal_single_issue_T": round(cus * 64 * 2.4e9 / 1e12, 2),
+        "ceilings_T": {
+            "full_rate_max": max(r["T_lane_ops_s"] for r in rows),
+            "v_bitop3_b32": best("v_bitop3_b32 xor3"),
+            "v_alignbit_b32": best("v_alignbit_b32 (sgpr shift)"),
+            "filter_mix_1_alignbit_2_bitop3": best("alignbit:bitop3 1:2"),
+        },
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_mscale(args):
@@ -670,14 +785,15 @@ def run_batched(args):
         # over their live duration
         "roofline": {"bound": "alu",
                      "achieved": None if valu is None else round(valu / (kern_ms / 1e3) / 1e12, 2),
-                     "peak": round(VALU_PEAK_TOPS, 1), "unit": "T int32 VALU lane-ops/s",
-                     "frac": None if valu is None else round(valu / (kern_ms / 1e3) / 1e12 / VALU_PEAK_TOPS, 4),
+                     "peak": valu_peak()["peak"], "unit": "T int32 VALU lane-ops/s",
+                     "frac": None if valu is None else round(valu / (kern_ms / 1e3) / 1e12 / valu_peak()["peak"], 4),
+                     "mix_ceiling": valu_peak()["mix"], "peak_source": valu_peak()["source"],
                      "traffic": None},
     }
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = host_threads()
         t0 = time.perf_counter()
         done = 0
         comps_cpu = 0.0
@@ -691,42 +807,30 @@ def run_batched(args):
                 break
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(comps_cpu / dt / 1e9, 3), "unit": "G comparisons/s",
-                                  "cores": threads, "kind": "oracle", "cpu": host_cpu_model(),
+                                  "cores": threads, "cpu_count": os.cpu_count(), "kind": "oracle",
+                                  "cpu": host_cpu_model(),
                                   "sample": f"first {done} patterns, windows [0, {win}) each, {dt:.1f} s"}
     return result
 
 
-def run_served(args):
-    """Queries from the pool arrive as a Poisson process at --qps for
-    --duration seconds and are served by the native engine (continuous
-    batching over revolving text chunks).  Reports the throughput in
-    comparisons/s over the whole run and the latency percentiles of the
-    queries (completion minus scheduled arrival)."""
+def serve(text, pats, ks, rate: float, duration: float, cfg, arena_gib: float, check_every: int = 32):
+    """Serve queries from the pool (pats, ks; cycled) arriving as a Poisson
+    process at `rate` per second for `duration` seconds through the native
+    engine (continuous batching over revolving text chunks).  Returns the
+    throughput over the whole run, the latency percentiles (completion minus
+    scheduled arrival) and the queueing delay; every check_every-th query's
+    result is compared with the plain kernel run alone on the same text."""
     import threading
 
     import numpy as np
-    import torch
 
     from paper_1611_06115_amd import scan, server, synth
 
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    n = args.n or 3_100_000_000
-    rate = float(args.qps)
-    t0 = time.perf_counter()
-    w = synth.served(n=n, count=args.count or 20000)
-    arrivals = synth.poisson_arrivals(rate, args.duration)
-    pats = [scan.Pattern(p) for p in w.patterns]
-    log(f"[bench] generated {n} bases, {len(pats)} pool queries, {arrivals.size} arrivals at {rate:g}/s "
-        f"in {time.perf_counter() - t0:.1f}s")
-    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
-    torch.cuda.synchronize()
-    text.check()
-    cfg = server.ServerConfig(chunks=args.chunks or 0, max_active=args.slots or 0,
-                              batch=scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0))
-    srv = server.Server(text, int(args.arena_gib * (1 << 30)), cfg)
+    n = text.n
+    arrivals = synth.poisson_arrivals(rate, duration)
+    srv = server.Server(text, int(arena_gib * (1 << 30)), cfg)
     for i in range(4):  # warm-up through the whole path (not timed)
-        srv.result(srv.submit(pats[i], w.ks[i]))
+        srv.result(srv.submit(pats[i], ks[i]))
     st0 = srv.stats()
     nq = int(arrivals.size)
     npool = len(pats)
@@ -742,7 +846,7 @@ def run_served(args):
                 if d <= 0:
                     break
                 time.sleep(d / 1e9 - 1e-4 if d > 300_000 else 0)
-            ids[i] = srv.submit(pats[i % npool], w.ks[i % npool], arrival_ns=due)
+            ids[i] = srv.submit(pats[i % npool], ks[i % npool], arrival_ns=due)
             submitted.release()
 
     th = threading.Thread(target=client, daemon=True)
@@ -751,7 +855,7 @@ def run_served(args):
     queue = np.zeros(nq)
     hits = np.zeros(nq, dtype=np.int64)
     last = start
-    every = max(1, nq // 32)
+    every = max(1, check_every)
     kept = {}
     done_log = time.perf_counter()
     for i in range(nq):
@@ -778,46 +882,90 @@ def run_served(args):
     comps = float(((n - ms_arr[idx] + 1).clip(min=0) * ms_arr[idx]).sum())
     log(f"[bench] {nq} queries in {elapsed:.2f}s, p50 {np.percentile(lat, 50):.1f} ms, "
         f"p99 {np.percentile(lat, 99):.1f} ms, {int(hits.sum())} hits, stats {st}")
-    # sampled queries: the planted site is found, and the result equals the
-    # plain kernel run alone on the same text, bit for bit
-    plant_of = {pi: (pos, d) for pi, pos, d in w.plants}
+    srv.close()
+    # sampled queries: the result equals the plain kernel run alone, bit for bit
     for i, (pos, cnt) in kept.items():
         qi = i % npool
-        ppos, _ = plant_of[qi]
-        if not bool((pos == ppos).any()):
-            raise SystemExit(f"query {i}: planted site {ppos} missed")
-        a_pos, a_cnt = scan.scan(text, pats[qi], w.ks[qi])
-        if not (torch.equal(a_pos, pos) and torch.equal(a_cnt, cnt)):
+        a_pos, a_cnt = scan.scan(text, pats[qi], ks[qi])
+        if not (torch_equal(a_pos, pos) and torch_equal(a_cnt, cnt)):
             raise SystemExit(f"query {i}: served result differs from the plain kernel alone")
-    log(f"[bench] {len(kept)} sampled queries equal to the plain kernel alone, plants found")
-    steps = st["steps"] - st0["steps"]
-    result = {
-        "metric": "G base-pattern comparisons/sec",
-        "value": round(comps / elapsed / 1e9, 1),
-        "unit": "G comparisons/s",
-        "n_gpus": 1, "steps": steps, "warmup": 4, "ms_per_step": round(elapsed * 1e3 / max(steps, 1), 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32 bitwise (exact integer counts)", "data": "synthetic",
+    log(f"[bench] {len(kept)} sampled queries equal to the plain kernel alone")
+    return {
+        "value": round(comps / elapsed / 1e9, 1), "elapsed_s": round(elapsed, 3),
+        "queries": nq, "qps_achieved": round(nq / elapsed, 1), "hits": int(hits.sum()),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                        "p99": round(float(np.percentile(lat, 99)), 2),
                        "mean": round(float(lat.mean()), 2), "max": round(float(lat.max()), 2)},
         "queue_ms": {"p50": round(float(np.percentile(queue, 50)), 2),
                      "p99": round(float(np.percentile(queue, 99)), 2)},
+        "stats": st, "stats0": st0, "kept": kept,
+        "checked": f"{len(kept)} sampled queries equal to the plain kernel run alone",
+    }
+
+
+def torch_equal(a, b) -> bool:
+    import torch
+
+    return bool(torch.equal(a, b))
+
+
+def run_served(args):
+    """Queries from the pool arrive as a Poisson process at --qps for
+    --duration seconds and are served by the native engine (continuous
+    batching over revolving text chunks).  Reports the throughput in
+    comparisons/s over the whole run and the latency percentiles of the
+    queries (completion minus scheduled arrival)."""
+    import torch
+
+    from paper_1611_06115_amd import scan, server, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n = args.n or 3_100_000_000
+    rate = float(args.qps)
+    t0 = time.perf_counter()
+    w = synth.served(n=n, count=args.count or 20000)
+    pats = [scan.Pattern(p) for p in w.patterns]
+    log(f"[bench] generated {n} bases and {len(pats)} pool queries in {time.perf_counter() - t0:.1f}s")
+    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
+    torch.cuda.synchronize()
+    text.check()
+    cfg = server.ServerConfig(chunks=args.chunks or 0, max_active=args.slots or 0,
+                              batch=scan.BatchConfig(args.group or 0, args.sub or 0, args.lane_words or 0, 0))
+    res = serve(text, pats, w.ks, rate, args.duration, cfg, args.arena_gib)
+    npool = len(pats)
+    # the sampled queries' planted sites are found
+    plant_of = {pi: (pos, d) for pi, pos, d in w.plants}
+    for i, (pos, cnt) in res["kept"].items():
+        ppos, _ = plant_of[i % npool]
+        if not bool((pos == ppos).any()):
+            raise SystemExit(f"query {i}: planted site {ppos} missed")
+    st, st0 = res["stats"], res["stats0"]
+    steps = st["steps"] - st0["steps"]
+    result = {
+        "metric": "G base-pattern comparisons/sec",
+        "value": res["value"],
+        "unit": "G comparisons/s",
+        "n_gpus": 1, "steps": steps, "warmup": 4, "ms_per_step": round(res["elapsed_s"] * 1e3 / max(steps, 1), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bitwise (exact integer counts)", "data": "synthetic",
+        "latency_ms": res["latency_ms"],
+        "queue_ms": res["queue_ms"],
         "config": {"workload": f"served: n={n} order-3 Markov GC 0.41 resident, Poisson arrivals at {rate:g}/s "
                                f"for {args.duration:g} s from a {npool}-query pool (m log-uniform 20..5000, "
                                f"k ~ U{{0..10}}, class density ~ U[0,0.3], one plant each)",
-                   "queries": nq, "qps_achieved": round(nq / elapsed, 1), "elapsed_s": round(elapsed, 3),
-                   "hits": int(hits.sum()), "chunks": st["chunks"], "slots": cfg.max_active or 1024,
+                   "queries": res["queries"], "qps_achieved": res["qps_achieved"], "elapsed_s": res["elapsed_s"],
+                   "hits": res["hits"], "chunks": st["chunks"], "slots": cfg.max_active or 1024,
                    "arena_gib": args.arena_gib, "peak_active": st["peak_active"],
-                   "reruns": st["reruns"] - st0["reruns"], "hit_slots_peak": st["hit_slots_peak"]},
-        "roofline": {"bound": "alu", "achieved": None, "peak": round(VALU_PEAK_TOPS, 1),
+                   "reruns": st["reruns"] - st0["reruns"], "hit_slots_peak": st["hit_slots_peak"],
+                   "checked": res["checked"]},
+        "roofline": {"bound": "alu", "achieved": None, "peak": valu_peak()["peak"],
                      "unit": "T int32 VALU lane-ops/s", "frac": None, "traffic": None},
     }
-    srv.close()
     if not args.no_cpu_baseline:
         import oracle
 
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads = host_threads()
         t0 = time.perf_counter()
         done = 0
         comps_cpu = 0.0
@@ -831,7 +979,8 @@ def run_served(args):
                 break
         dt = time.perf_counter() - t0
         result["cpu_baseline"] = {"value": round(comps_cpu / dt / 1e9, 3), "unit": "G comparisons/s",
-                                  "cores": threads, "kind": "oracle", "cpu": host_cpu_model(),
+                                  "cores": threads, "cpu_count": os.cpu_count(), "kind": "oracle",
+                                  "cpu": host_cpu_model(),
                                   "sample": f"first {done} pool queries, windows [0, {win}) each, {dt:.1f} s"}
     return result
 
@@ -859,11 +1008,17 @@ def main():
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-served", action="store_true", help="genome: skip the served-latency leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter scaling)")
+    ap.add_argument("--valu-calibration", action="store_true",
+                    help="only measure the VALU issue rates of the kernels' instructions (alu peaks)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.valu_calibration:
+        valu_calibration()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards "

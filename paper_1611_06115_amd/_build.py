@@ -32,6 +32,19 @@ def build(extra: list[str] | None = None, out: str = LIB) -> str:
     return out
 
 
+CALIB_LIB = os.path.join(HERE, "libpmcalib.so")
+
+
+def build_calib() -> str:
+    """The VALU issue-rate probe (csrc/calib.hip) used by
+    bench.py --valu-calibration; not part of the scan library."""
+    tmp = CALIB_LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, os.path.join(CSRC, "calib.hip"), "-o", tmp]
+    subprocess.check_call(cmd)
+    os.replace(tmp, CALIB_LIB)
+    return CALIB_LIB
+
+
 def build_c_client() -> str:
     """The test client that uses only the C ABI (tests/c_client), linked to
     the library in place."""

@@ -137,11 +137,20 @@ def tune(text: Text, batch: Batch, candidates=None, sample_windows: int | None =
                                        win_begin=0, win_end=sample_windows, config=cfg, stream=stream)
         run()
         stream.synchronize()
+        # every shape must give the same lists: totals, completion, and each
+        # complete pattern's positions and counts
         totals = n_hits.cpu().numpy().copy()
+        done = status.cpu().numpy() == 0
+        lists = [(pos[int(o):int(o) + int(h)].cpu().numpy(), cnt[int(o):int(o) + int(h)].cpu().numpy())
+                 if d else None for o, h, d in zip(batch.out_off, totals, done)]
         if reference is None:
-            reference = totals
-        elif not np.array_equal(reference, totals):
-            raise RuntimeError(f"batch shape {cand} changed the hit totals")
+            reference = (totals, lists)
+        else:
+            same = np.array_equal(reference[0], totals) and all(
+                (a is None or b is None) or (np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]))
+                for a, b in zip(reference[1], lists))
+            if not same:
+                raise RuntimeError(f"batch shape {cand} changed the hit lists")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)

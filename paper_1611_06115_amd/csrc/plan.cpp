@@ -141,6 +141,94 @@ void build_image(const uint8_t* codes, uint32_t m, uint32_t* out) {
     }
 }
 
+namespace {
+
+// Selectivity prior of the planner: the base composition of a genome-like
+// text (GC 41%, the human average).  A singleton position of base c then
+// mismatches a random text base with probability 1 - kBaseFreq[c]; it only
+// steers which positions the filter takes (results never depend on it).
+constexpr double kBaseFreq[4] = {0.295, 0.205, 0.205, 0.295};
+
+// Probability that at most K-1 of the given independent positions mismatch.
+double survival_of(const std::vector<double>& pmm, uint32_t K) {
+    std::vector<double> d(K + 1, 0.0);
+    d[0] = 1.0;
+    for (double q : pmm)
+        for (int c = static_cast<int>(K); c >= 0; --c)
+            d[c] = d[c] * (1.0 - q) + (c > 0 ? d[c - 1] * q : 0.0);
+    double tot = 0;
+    for (uint32_t c = 0; c < K; ++c) tot += d[c];
+    return tot;
+}
+
+// Singleton filter made only of full sets (4 positions of one base and one
+// word of the filter window) in whole groups (2 sets), 1 to 4 groups: the
+// shape the unrolled filter kernel takes.  Over every filter window, the
+// fewest groups whose survival (under kBaseFreq) is at most `survival`, the
+// most selective sets first; ties go to the lower survival.  Fills p and
+// returns true when some window reaches the target this way.
+bool full_set_plan(const std::vector<unsigned>& mm, uint32_t m, uint32_t K, double survival,
+                   bool window_at_zero, ScanPlan& p) {
+    struct Set {
+        uint32_t cq;
+        uint32_t r[4];
+        double pmm;
+    };
+    uint32_t best_groups = 5, best_fw = 0;
+    double best_surv = 2.0;
+    std::vector<Set> best_sets;
+    for (uint32_t fw = 0; 32 * fw < m && (fw == 0 || !window_at_zero); fw += 2) {
+        std::vector<uint32_t> cls[8];
+        for (uint32_t j = 32 * fw; j < std::min(m, 32 * fw + 64); ++j) {
+            if (__builtin_popcount(mm[j]) != 3) continue;
+            const uint32_t rel = j - 32 * fw;
+            const unsigned base = static_cast<unsigned>(__builtin_ctz(~mm[j] & 15u));
+            cls[base | ((rel >> 5) << 2)].push_back(rel & 31u);
+        }
+        std::vector<Set> sets;
+        for (uint32_t cq = 0; cq < 8; ++cq)
+            for (size_t t = 0; t + 4 <= cls[cq].size(); t += 4)
+                sets.push_back({cq, {cls[cq][t], cls[cq][t + 1], cls[cq][t + 2], cls[cq][t + 3]},
+                                1.0 - kBaseFreq[cq & 3u]});
+        std::stable_sort(sets.begin(), sets.end(), [](const Set& a, const Set& b) { return a.pmm > b.pmm; });
+        std::vector<double> pmm;
+        for (uint32_t g = 1; g <= 4 && 2 * g <= sets.size() && g <= best_groups; ++g) {
+            for (uint32_t t = 2 * (g - 1); t < 2 * g; ++t)
+                for (int u = 0; u < 4; ++u) pmm.push_back(sets[t].pmm);
+            const double sv = survival_of(pmm, K);
+            if (sv <= survival) {
+                if (g < best_groups || sv < best_surv) {
+                    best_groups = g;
+                    best_surv = sv;
+                    best_fw = fw;
+                    best_sets.assign(sets.begin(), sets.begin() + 2 * g);
+                }
+                break;
+            }
+        }
+    }
+    if (best_groups > 4) return false;
+    uint32_t L = 0;
+    while ((1u << L) < K) ++L;
+    p.levels = L;
+    p.init = (1u << L) - K;
+    p.fword = best_fw;
+    p.n_slots = 8 * best_groups;
+    p.n_sets = 2 * best_groups;
+    p.n_groups = best_groups;
+    p.singles = 0;
+    for (uint32_t t = 0; t < p.n_sets; ++t) {
+        const Set& st = best_sets[t];
+        uint32_t w = st.cq | (4u << 3);
+        for (int u = 0; u < 4; ++u) w |= st.r[u] << (6 + 5 * u);
+        p.slot[t] = w;
+        p.singles |= 1u << (st.cq & 3u);
+    }
+    return true;
+}
+
+}  // namespace
+
 ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double survival, bool window_at_zero) {
     ScanPlan p;
     std::memset(&p, 0, sizeof(p));
@@ -232,6 +320,7 @@ ScanPlan build_plan(const uint8_t* codes, uint32_t m, uint32_t k, double surviva
         return p;
     }
     p.exhaustive = 0;
+    if (J > 0 && full_set_plan(mm, m, K, survival, window_at_zero, p)) return p;
     p.fword = best_fw;
     p.n_slots = J;
     if (J > 0) {

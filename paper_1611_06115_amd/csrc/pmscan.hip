@@ -38,6 +38,7 @@
 #include "../../include/pmscan.h"
 #include "plan.hpp"
 #include "scan_core.hpp"
+#include "scan_kernels.hpp"
 
 namespace pm {
 uint64_t resident_blocks(const void* fn);
@@ -48,7 +49,6 @@ using namespace pm;
 
 namespace {
 
-constexpr int TPB = pm::kThreads;
 constexpr uint64_t kPadBlocks = 64;  // zero blocks after the text (16-byte loads, halos)
 
 thread_local std::string g_detail;
@@ -155,300 +155,8 @@ __global__ void encode_text_kernel(const uint8_t* __restrict__ ascii, uint64_t n
 }
 
 // ---------------------------------------------------------------------------
-// scan
+// scan: the kernels are in scan_kernels.hpp
 // ---------------------------------------------------------------------------
-
-constexpr int kCap = 32;      // hits a tile stages for the placement kernel
-constexpr uint32_t kMaxRanges = 16384;  // workgroups of a count-kernel grid (workspace holds one sum each)
-
-struct ScanArgs {
-    TileSrc src;               // text (16-byte groups), pattern image, window range
-    const uint4* text4;        // = src.text4
-    uint64_t n4;               // 16-byte groups in the buffer
-    uint64_t wb0;              // first block of tile 0 (even)
-    uint64_t win_begin, win_end;
-    int64_t* pos;
-    uint16_t* cnt;
-    uint64_t capacity;
-    unsigned long long* n_hits;
-    uint32_t* counts;                // hits per tile
-    unsigned long long* range_sum;   // hits per count-kernel workgroup (its range of tiles)
-    unsigned long long* staged;      // kCap per tile: (window offset << 16) | count
-    uint32_t n_tiles, n_ranges;
-};
-
-// The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
-// (B and fw are even).  Lanes past the end of the text read the last group.
-template <int R>
-__device__ __forceinline__ void load_text(const ScanArgs& a, const ScanPlan& p, uint64_t B,
-                                          uint4 (&t)[(R + 2) / 2]) {
-    const uint64_t g0 = (B + p.fword) >> 1;
-#pragma unroll
-    for (int u = 0; u < (R + 2) / 2; ++u) {
-        uint64_t gi = g0 + u;
-        if (gi >= a.n4) gi = a.n4 - 1;
-        t[u] = a.text4[gi];
-    }
-}
-
-// The same for a whole tile starting at block T0 (wave-uniform): tiles that
-// end before the last 16-byte group need no clamping.
-template <int R>
-__device__ __forceinline__ void load_tile_text(const ScanArgs& a, const ScanPlan& p, uint64_t T0,
-                                               uint4 (&t)[(R + 2) / 2]) {
-    // group indices fit in 32 bits (texts below 2^37 bases); clamping is one
-    // v_min per load and only changes anything in the last tile
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t g0 = (uint32_t)((T0 + p.fword) >> 1) + lane * (R / 2);
-    const uint32_t last = (uint32_t)(a.n4 - 1);
-#pragma unroll
-    for (int u = 0; u < (R + 2) / 2; ++u) t[u] = a.text4[min(g0 + (uint32_t)u, last)];
-}
-
-// Write the hits of this lane, in order, starting at output index `idx`.
-template <int R, int L, bool EXH>
-__device__ __forceinline__ void write_hits(const ScanArgs& a, const ScanPlan& p, const Counters<R, L>& C,
-                                           const uint32_t (&hit)[R], uint64_t B, unsigned long long idx) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) {
-        uint32_t h = hit[i];
-        while (h) {
-            const uint32_t b = __builtin_ctz(h);
-            h &= h - 1u;
-            if (idx < a.capacity) {
-                const uint64_t pos = 32 * (B + i) + b;
-                a.pos[idx] = (int64_t)pos;
-                a.cnt[idx] = (uint16_t)hit_count<R, L, EXH>(a.src, p, C, i, b, pos);
-            }
-            ++idx;
-        }
-    }
-}
-
-// A tile is the 64 lanes of one wave, R lane words (32 windows) each.
-__device__ __forceinline__ uint64_t tile_first_block(const ScanArgs& a, uint32_t tile, int R) {
-    return a.wb0 + (uint64_t)tile * (uint64_t)(64 * R);
-}
-
-__device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint64_t T0, int R) {
-    return 32 * T0 >= a.win_begin && 32 * (T0 + 64 * (uint64_t)R) <= a.win_end;
-}
-
-// Exclusive prefix of `x` over the lanes of a wave; `total` gets the sum.
-__device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t v = __shfl_up(incl, d, 64);
-        if (lane >= (uint32_t)d) incl += v;
-    }
-    total = __shfl(incl, 63, 64);
-    return incl - x;
-}
-
-// Pass 1: every tile (one wave's windows) finds its hits, stores their number,
-// and stages them when there are at most kCap.  Waves are persistent and
-// independent: each workgroup takes a contiguous range of tiles, its waves
-// take every 4th tile of it in order, and the workgroup stores the total hit
-// count of its range.
-// With 4 lane words and up to 3 counter levels the kernel is held to 5 waves
-// per SIMD (its registers fit; measured faster than 4 waves); other shapes
-// keep the compiler's choice.
-template <int R, int L, bool EXH>
-__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(R == 4 && L <= 3 ? 5 : 1)))
-void scan_count_kernel(ScanArgs a, ScanPlan p) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform
-    // workgroup b takes tiles [b T / G, (b+1) T / G) of the G in the grid;
-    // its waves interleave in that range
-    constexpr uint32_t kStep = TPB / 64;
-    const uint32_t t_end = (uint32_t)((uint64_t)(blockIdx.x + 1) * a.n_tiles / gridDim.x);
-    uint32_t tile = (uint32_t)((uint64_t)blockIdx.x * a.n_tiles / gridDim.x) + wv;
-    uint32_t sum = 0;
-    __shared__ unsigned long long s_vh[TPB / 64][kWaveHits];  // hits kept by tile_filter, per wave
-    // the text of the wave's next tile is loaded while this one is computed
-    uint4 nxt[(R + 2) / 2];
-    if (tile < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile, R), nxt);
-    for (; tile < t_end; tile += kStep) {
-        const uint64_t T0 = tile_first_block(a, tile, R);
-        const uint64_t B = T0 + (uint64_t)lane * R;
-        uint4 txt[(R + 2) / 2];
-#pragma unroll
-        for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = nxt[u];
-        if (tile + kStep < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile + kStep, R), nxt);
-        // keep those loads here, ahead of the filter (the scheduler would
-        // otherwise sink them below it, next to their use)
-        __builtin_amdgcn_sched_barrier(0);
-        Counters<R, L> C;
-        uint32_t hit[R], nh;
-        Lane<R> s;
-        make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-        uint32_t nvh = 0;
-        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh, s_vh[wv], &nvh);
-        if (__ballot(nh != 0) == 0) {  // the usual case: no hits in the tile
-            if (lane == 0) a.counts[tile] = 0;
-            continue;
-        }
-        uint32_t total;
-        const uint32_t excl = wave_exclusive(nh, total);
-        if (lane == 0) a.counts[tile] = total;
-        sum += total;
-        if (total > (uint32_t)kCap) continue;
-        const uint64_t base = 32 * T0;
-        if (!EXH && p.nchunks > kWaveVerifyChunks) {
-            unsigned long long* out = a.staged + (uint64_t)tile * kCap;
-            if (nvh == total && total <= kWaveHits) {
-                // every hit was counted by the whole wave and kept, in order
-                if (lane < total) {
-                    const unsigned long long v = s_vh[wv][lane];
-                    out[lane] = (((v >> 16) - base) << 16) | (v & 0xFFFFu);
-                }
-                continue;
-            }
-            // otherwise: the hits in position order (the staging order), each
-            // counted by the whole wave and written by its lane
-            for (uint32_t j = 0;; ++j) {
-                uint32_t mine = 0;
-#pragma unroll
-                for (int i = 0; i < R; ++i) mine |= hit[i];
-                const uint64_t bal = __ballot(mine != 0);
-                if (bal == 0) break;
-                const uint32_t owner = (uint32_t)__builtin_ctzll(bal);
-                int fi = 0;
-                uint32_t fb = 0;
-#pragma unroll
-                for (int i = R - 1; i >= 0; --i)
-                    if (hit[i]) {
-                        fi = i;
-                        fb = __builtin_ctz(hit[i]);
-                    }
-                const uint64_t mine_pos = 32 * (B + (uint64_t)fi) + fb;
-                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine_pos, owner);
-                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine_pos >> 32), owner);
-                const uint64_t pos = ((uint64_t)hi << 32) | lo;
-                const uint32_t c = count_window_wave(a.src.text4, a.src.image, p.nchunks, pos, p.k, lane);
-                if (lane == owner) {
-                    out[j] = ((pos - base) << 16) | c;
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == fi) hit[i] &= hit[i] - 1u;
-                }
-            }
-            continue;
-        }
-        if (nh == 0) continue;
-        unsigned long long* out = a.staged + (uint64_t)tile * kCap + excl;
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            uint32_t h = hit[i];
-            while (h) {
-                const uint32_t b = __builtin_ctz(h);
-                h &= h - 1u;
-                const uint64_t pos = 32 * (B + i) + b;
-                const uint32_t c = hit_count<R, L, EXH>(a.src, p, C, i, b, pos);
-                *out++ = ((pos - base) << 16) | c;
-            }
-        }
-    }
-    // the workgroup's total: one sum per range
-    __shared__ uint32_t s_sum[TPB / 64];
-    if (lane == 0) s_sum[threadIdx.x >> 6] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-#pragma unroll
-        for (int i = 0; i < TPB / 64; ++i) t += s_sum[i];
-        a.range_sum[blockIdx.x] = t;
-    }
-}
-
-// Wave sum of x[first .. last) (all 64 lanes of one wave call it).
-template <typename T>
-__device__ __forceinline__ unsigned long long wave_sum(const T* x, uint64_t first, uint64_t last) {
-    const uint32_t lane = threadIdx.x & 63u;
-    // four loads per lane in flight at a time
-    unsigned long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-    uint64_t i = first + lane;
-    for (; i + 192 < last; i += 256) {
-        v0 += x[i];
-        v1 += x[i + 64];
-        v2 += x[i + 128];
-        v3 += x[i + 192];
-    }
-    for (; i < last; i += 64) v0 += x[i];
-    unsigned long long v = (v0 + v1) + (v2 + v3);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
-// Pass 3: each wave takes 64 consecutive tiles and ranks their hit counts;
-// every tile with hits then has them placed at its ordered offset -- copied
-// from the staging area, or, for a tile with more than kCap hits, found again
-// by the wave and written directly.  Waves of segments without hits return
-// after one load.
-template <int R, int L, bool EXH>
-__global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p) {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t seg = (uint64_t)blockIdx.x * (TPB / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const uint64_t t0 = seg * 64;
-    if (seg == 0) {
-        const unsigned long long all = wave_sum(a.range_sum, 0, a.n_ranges);
-        if (lane == 0) *a.n_hits = all;
-    }
-    if (t0 >= a.n_tiles) return;
-    const uint32_t count = t0 + lane < a.n_tiles ? a.counts[t0 + lane] : 0u;
-    unsigned long long busy = __ballot(count != 0);
-    if (busy == 0) return;
-    // hits before tile t0: the ranges of the count kernel's workgroups before
-    // the one that owns t0 (the last whose range starts at or before t0), then
-    // that range's tiles before t0
-    const uint32_t G = a.n_ranges;
-    uint32_t b0 = (uint32_t)(t0 * G / a.n_tiles);
-    while (b0 + 1 < G && (uint64_t)(b0 + 1) * a.n_tiles / G <= t0) ++b0;
-    const uint64_t s0 = (uint64_t)b0 * a.n_tiles / G;
-    const unsigned long long base = wave_sum(a.range_sum, 0, b0) + wave_sum(a.counts, s0, t0);
-    unsigned long long incl = count;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const unsigned long long v = __shfl_up(incl, d, 64);
-        if (lane >= (uint32_t)d) incl += v;
-    }
-    const unsigned long long first = base + incl - count;  // output index of this lane's tile
-    while (busy) {
-        const uint32_t l = __builtin_ctzll(busy);
-        busy &= busy - 1ull;
-        const uint32_t cl = __shfl(count, (int)l, 64);
-        const unsigned long long pl = __shfl(first, (int)l, 64);
-        if (pl >= a.capacity) break;  // later tiles start even later
-        const uint32_t tile = (uint32_t)(t0 + l);
-        const uint64_t T0 = tile_first_block(a, tile, R);
-        if (cl <= (uint32_t)kCap) {
-            const unsigned long long* src = a.staged + (uint64_t)tile * kCap;
-            for (uint32_t i = lane; i < cl; i += 64) {
-                const unsigned long long v = src[i];
-                const unsigned long long dst = pl + i;
-                if (dst < a.capacity) {
-                    a.pos[dst] = (int64_t)(32 * T0 + (v >> 16));
-                    a.cnt[dst] = (uint16_t)(v & 0xFFFFu);
-                }
-            }
-        } else {
-            const uint64_t B = T0 + (uint64_t)lane * R;
-            uint4 txt[(R + 2) / 2];
-            load_text<R>(a, p, B, txt);
-            Counters<R, L> C;
-            uint32_t hit[R], nh;
-            Lane<R> s;
-            make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-            tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
-            uint32_t total;
-            const uint32_t excl = wave_exclusive(nh, total);
-            if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, pl + excl);
-        }
-    }
-}
 
 #ifndef PMSCAN_LANE_WORDS
 #define PMSCAN_LANE_WORDS 4
@@ -468,9 +176,40 @@ ScanPair pick_scan_l(uint32_t L) {
         default: return {nullptr, nullptr};
     }
 }
+// Count kernels with the fixed filter: singleton plans of NG = 1..4 groups of
+// full sets and 1..4 counter levels (k - #'-' up to 15).
+template <int R, int NG>
+ScanFn pick_fixed_l(uint32_t L) {
+    switch (L) {
+        case 1: return scan_fixed_kernel<R, 1, NG>;
+        case 2: return scan_fixed_kernel<R, 2, NG>;
+        case 3: return scan_fixed_kernel<R, 3, NG>;
+        case 4: return scan_fixed_kernel<R, 4, NG>;
+        default: return nullptr;
+    }
+}
+template <int R>
+ScanFn pick_fixed(const ScanPlan& p) {
+#ifdef PM_NO_FIXED
+    return nullptr;
+#endif
+    if (p.exhaustive || p.n_slots == 0 || p.n_sets != 2 * p.n_groups || p.n_slots != 8 * p.n_groups) return nullptr;
+    for (uint32_t t = 0; t < p.n_sets; ++t)
+        if ((p.slot[t] >> 3 & 7u) != 4u) return nullptr;
+    switch (p.n_groups) {
+        case 1: return pick_fixed_l<R, 1>(p.levels);
+        case 2: return pick_fixed_l<R, 2>(p.levels);
+        case 3: return pick_fixed_l<R, 3>(p.levels);
+        case 4: return pick_fixed_l<R, 4>(p.levels);
+        default: return nullptr;
+    }
+}
 template <int R>
 ScanPair pick_scan(const ScanPlan& p) {
-    return p.exhaustive ? pick_scan_l<R, true>(p.levels) : pick_scan_l<R, false>(p.levels);
+    ScanPair f = p.exhaustive ? pick_scan_l<R, true>(p.levels) : pick_scan_l<R, false>(p.levels);
+    if (f.count)
+        if (ScanFn fixed = pick_fixed<R>(p)) f.count = fixed;
+    return f;
 }
 
 // Workgroups for a persistent kernel: as many as fit on the device at once
@@ -532,15 +271,15 @@ uint64_t max_tiles(uint64_t n) {
     return (blocks + 64ull * kR - 1) / (64ull * kR) + 1;
 }
 
-uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
 // Workspace layout for up to T tiles: hit counts (u32 per tile), hit sums
 // (u64 per count-kernel workgroup), staged hits (kCap u64 per tile).
 struct WsLayout {
     uint64_t counts, range_sum, staged, bytes;
 };
-WsLayout ws_layout(uint64_t T) {
-    WsLayout w;
+constexpr WsLayout ws_layout(uint64_t T) {
+    WsLayout w{};
     w.counts = 0;
     w.range_sum = align256(4 * T);
     w.staged = w.range_sum + align256(8ull * kMaxRanges);
@@ -589,6 +328,78 @@ hipError_t mark_end(hipStream_t s) {
     return e;
 }
 }  // namespace pm
+
+// ---------------------------------------------------------------------------
+// the scan launch over a workspace of a given layout
+// ---------------------------------------------------------------------------
+namespace {
+
+// One scan: argument checks, the plan, the count and place kernels on
+// stream `stream`.  `ws` holds lay.bytes bytes; tile_limit > 0 bounds the
+// tiles of the window range (a layout sized for a fixed number of tiles), 0
+// means the layout was sized from n (any range of the text fits).
+pm_status scan_launch(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m, uint32_t k,
+                      const void* image_dev, uint64_t win_begin, uint64_t win_end, int64_t* pos_dev,
+                      uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev, uint8_t* ws,
+                      const WsLayout& lay, uint64_t tile_limit, void* stream) {
+    if (!text_dev || !codes || !image_dev || !n_hits_dev) return fail(PM_ERR_ARG, "null pointer");
+    if (capacity > 0 && (!pos_dev || !cnt_dev)) return fail(PM_ERR_ARG, "null output with capacity > 0");
+    if (m == 0) return fail(PM_ERR_ARG, "empty pattern (m = 0)");
+    if (k > 65535) return fail(PM_ERR_ARG, "k above 65535 (counts are 16-bit)");
+    if (reinterpret_cast<uintptr_t>(text_dev) % 16 != 0)
+        return fail(PM_ERR_ARG, "text_dev must be 16-byte aligned");
+    if (reinterpret_cast<uintptr_t>(image_dev) % 16 != 0)
+        return fail(PM_ERR_ARG, "image_dev must be 16-byte aligned");
+    if (text_blocks(n) / 2 >= (1ull << 32)) return fail(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    const uint64_t nw = m <= n ? n - m + 1 : 0;
+    if (win_end > nw) win_end = nw;
+    ScanPlan plan;
+    if (const pm_status st = scan_plan(codes, m, k, plan); st != PM_OK) return st;
+    if (win_begin >= win_end || plan.keff < 0) return fill_u64(n_hits_dev, 0, 1, s);
+
+    const uint64_t wb0 = (win_begin >> 5) & ~1ull;
+    const uint64_t wb_end = (win_end + 31) >> 5;
+    const uint64_t tile_blocks = 64ull * kR;
+    const uint64_t n_tiles = (wb_end - wb0 + tile_blocks - 1) / tile_blocks;
+    if (n_tiles > (tile_limit ? tile_limit : max_tiles(n)) || n_tiles > 0xFFFFFFFFull)
+        return fail(PM_ERR_ARG, "window range too large");
+
+    const ScanPair fn = pick_scan<kR>(plan);
+    if (!fn.count) return fail(PM_ERR_UNSUPPORTED, "counter levels out of range");
+
+    ScanArgs a;
+    a.text4 = reinterpret_cast<const uint4*>(text_dev);
+    a.src.text4 = a.text4;
+    a.src.image = reinterpret_cast<const uint4*>(image_dev);
+    a.src.win_begin = win_begin;
+    a.src.win_end = win_end;
+    a.n4 = text_blocks(n) / 2;
+    a.wb0 = wb0;
+    a.win_begin = win_begin;
+    a.win_end = win_end;
+    a.pos = pos_dev;
+    a.cnt = cnt_dev;
+    a.capacity = capacity;
+    a.n_hits = reinterpret_cast<unsigned long long*>(n_hits_dev);
+    a.counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
+    a.range_sum = reinterpret_cast<unsigned long long*>(ws + lay.range_sum);
+    a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
+    a.n_tiles = (uint32_t)n_tiles;
+    const unsigned grid = persistent_grid(fn.count, n_tiles);
+    a.n_ranges = grid;
+
+    HIP_TRY(pm::mark_begin(s));
+    fn.count<<<grid, TPB, 0, s>>>(a, plan);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(pm::mark_end(s));
+    fn.place<<<(unsigned)((n_tiles + 64 * (TPB / 64) - 1) / (64 * (TPB / 64))), TPB, 0, s>>>(a, plan);
+    HIP_TRY(hipGetLastError());
+    return PM_OK;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -679,64 +490,10 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
                   const void* image_dev, uint64_t win_begin, uint64_t win_end, int64_t* pos_dev,
                   uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev, void* ws_dev,
                   uint64_t ws_bytes, void* stream) {
-    if (!text_dev || !codes || !image_dev || !n_hits_dev || !ws_dev)
-        return fail(PM_ERR_ARG, "null pointer");
-    if (capacity > 0 && (!pos_dev || !cnt_dev)) return fail(PM_ERR_ARG, "null output with capacity > 0");
-    if (m == 0) return fail(PM_ERR_ARG, "empty pattern (m = 0)");
-    if (k > 65535) return fail(PM_ERR_ARG, "k above 65535 (counts are 16-bit)");
-    if (reinterpret_cast<uintptr_t>(text_dev) % 16 != 0)
-        return fail(PM_ERR_ARG, "text_dev must be 16-byte aligned");
-    if (reinterpret_cast<uintptr_t>(image_dev) % 16 != 0)
-        return fail(PM_ERR_ARG, "image_dev must be 16-byte aligned");
+    if (!ws_dev) return fail(PM_ERR_ARG, "null pointer");
     if (ws_bytes < pm_scan_workspace_bytes(n)) return fail(PM_ERR_WORKSPACE, "workspace too small");
-    if (text_blocks(n) / 2 >= (1ull << 32)) return fail(PM_ERR_UNSUPPORTED, "texts are limited to 2^37 bases");
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-
-    const uint64_t nw = m <= n ? n - m + 1 : 0;
-    if (win_end > nw) win_end = nw;
-    ScanPlan plan;
-    if (const pm_status st = scan_plan(codes, m, k, plan); st != PM_OK) return st;
-    if (win_begin >= win_end || plan.keff < 0) return fill_u64(n_hits_dev, 0, 1, s);
-
-    const uint64_t wb0 = (win_begin >> 5) & ~1ull;
-    const uint64_t wb_end = (win_end + 31) >> 5;
-    const uint64_t tile_blocks = 64ull * kR;
-    const uint64_t n_tiles = (wb_end - wb0 + tile_blocks - 1) / tile_blocks;
-    if (n_tiles > max_tiles(n) || n_tiles > 0xFFFFFFFFull) return fail(PM_ERR_ARG, "window range too large");
-
-    const ScanPair fn = pick_scan<kR>(plan);
-    if (!fn.count) return fail(PM_ERR_UNSUPPORTED, "counter levels out of range");
-
-    uint8_t* ws = reinterpret_cast<uint8_t*>(ws_dev);
-    const WsLayout lay = ws_layout(max_tiles(n));
-    ScanArgs a;
-    a.text4 = reinterpret_cast<const uint4*>(text_dev);
-    a.src.text4 = a.text4;
-    a.src.image = reinterpret_cast<const uint4*>(image_dev);
-    a.src.win_begin = win_begin;
-    a.src.win_end = win_end;
-    a.n4 = text_blocks(n) / 2;
-    a.wb0 = wb0;
-    a.win_begin = win_begin;
-    a.win_end = win_end;
-    a.pos = pos_dev;
-    a.cnt = cnt_dev;
-    a.capacity = capacity;
-    a.n_hits = reinterpret_cast<unsigned long long*>(n_hits_dev);
-    a.counts = reinterpret_cast<uint32_t*>(ws + lay.counts);
-    a.range_sum = reinterpret_cast<unsigned long long*>(ws + lay.range_sum);
-    a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
-    a.n_tiles = (uint32_t)n_tiles;
-    const unsigned grid = persistent_grid(fn.count, n_tiles);
-    a.n_ranges = grid;
-
-    HIP_TRY(pm::mark_begin(s));
-    fn.count<<<grid, TPB, 0, s>>>(a, plan);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(pm::mark_end(s));
-    fn.place<<<(unsigned)((n_tiles + 64 * (TPB / 64) - 1) / (64 * (TPB / 64))), TPB, 0, s>>>(a, plan);
-    HIP_TRY(hipGetLastError());
-    return PM_OK;
+    return scan_launch(text_dev, n, codes, m, k, image_dev, win_begin, win_end, pos_dev, cnt_dev, capacity,
+                       n_hits_dev, reinterpret_cast<uint8_t*>(ws_dev), ws_layout(max_tiles(n)), 0, stream);
 }
 
 }  // extern "C"

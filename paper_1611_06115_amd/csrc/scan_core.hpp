@@ -282,6 +282,89 @@ __device__ __forceinline__ void make_lane(const uint4 (&t)[(R + 2) / 2], uint32_
     }
 }
 
+// Survivors of a singleton filter (windows whose bit in dead[] is clear) ->
+// hits: each is counted exactly over all m positions and kept when the count
+// is at most k.  hit[i] gets the hits of lane word i, nh the lane's number of
+// hits.  With WV and a pattern of more than kWaveVerifyChunks chunks, a wave
+// with survivors in at most kWaveVerifyLanes lanes counts them one at a time
+// with all its lanes (position order), keeping the first kWaveHits hits as
+// (position << 16 | count) in vh (count of all such hits in *nvh); dead[] is
+// consumed.  Otherwise each lane counts its own survivors.
+template <int R, bool WV, class Plan>
+__device__ __forceinline__ void verify_survivors(const TileSrc& src, const Plan& p, uint64_t B, uint32_t (&dead)[R],
+                                                 uint32_t (&hit)[R], uint32_t& nh, unsigned long long* vh = nullptr,
+                                                 uint32_t* nvh = nullptr) {
+    nh = 0;
+    uint32_t any = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) any |= ~dead[i];
+    if (vh) *nvh = 0;
+    if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
+#pragma unroll
+        for (int i = 0; i < R; ++i) hit[i] = 0;
+        return;
+    }
+    if (WV && p.nchunks > kWaveVerifyChunks && __popcll(__ballot(any != 0)) <= kWaveVerifyLanes) {
+        // survivors in position order (lowest lane first, then its words
+        // and bits), each counted by the whole wave; a verified survivor
+        // is marked dead, a hit set in hit[]
+        const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+        for (int i = 0; i < R; ++i) hit[i] = 0;
+        for (;;) {
+            uint32_t mine = 0;
+#pragma unroll
+            for (int i = 0; i < R; ++i) mine |= ~dead[i];
+            const uint64_t bal = __ballot(mine != 0);
+            if (bal == 0) break;
+            const uint32_t owner = (uint32_t)__builtin_ctzll(bal);
+            int fi = 0;
+            uint32_t fb = 0;
+#pragma unroll
+            for (int i = R - 1; i >= 0; --i)
+                if (~dead[i]) {
+                    fi = i;
+                    fb = __builtin_ctz(~dead[i]);
+                }
+            const uint64_t mine_pos = 32 * (B + (uint64_t)fi) + fb;
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine_pos, owner);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine_pos >> 32), owner);
+            const uint64_t pos = ((uint64_t)hi << 32) | lo;
+            const uint32_t c = count_window_wave(src.text4, src.image, p.nchunks, pos, p.k, lane);
+            if (lane == owner) {
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (i == fi) {
+                        dead[i] |= 1u << fb;
+                        if (c <= p.k) hit[i] |= 1u << fb;
+                    }
+            }
+            // hits come in position order: the first kWaveHits are kept
+            // (position << 16 | count) for the caller's output
+            if (vh && c <= p.k) {
+                if (*nvh < kWaveHits && lane == owner) vh[*nvh] = (pos << 16) | c;
+                ++*nvh;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) nh += __builtin_popcount(hit[i]);
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        uint32_t alive = ~dead[i];
+        uint32_t h = 0;
+        while (alive) {
+            const uint32_t b = __builtin_ctz(alive);
+            alive &= alive - 1u;
+            const uint32_t c = count_window(src.text4, src.image, p.nchunks, 32 * (B + i) + b, p.k);
+            if (c <= p.k) h |= 1u << b;
+        }
+        hit[i] = h;
+        nh += __builtin_popcount(h);
+    }
+}
+
 // Filter + verification of one tile for one pattern: hit[i] gets the windows
 // of lane word i (window 32*(B+i) + bit) with at most k mismatches; C keeps the
 // filter counters (the exact counts when the plan is exhaustive).  `s` holds
@@ -371,74 +454,106 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, u
             nh += __builtin_popcount(hit[i]);
         }
     } else {
-        uint32_t any = 0;
+        verify_survivors<R, WV>(src, p, B, C.dead, hit, nh, vh, nvh);
+    }
+}
+
+// Singleton filter with a structure fixed at compile time: NG groups of two
+// full sets (8 positions each, slot words sw[0 .. 2 NG) of the plan, uniform),
+// counters started at the plan's init (uniform: every level all ones or all
+// zeros), no window excluded.  dead[i] gets the windows of lane word i whose
+// count over the 8 NG positions reaches keff + 1.
+//
+// The mismatch planes of the bases the plan uses go to this wave's region of
+// LDS (`planes`: [base][word][lane], 4 x (R+2) x 64 words) instead of
+// registers, so that a set reads the R+1 words of its base and word offset at
+// a uniform address: no branch on the set's base, and no planes held in
+// registers across the filter.  The loops are unrolled, so that the first
+// group reads the uniform start values directly and the last group's counter
+// sums, which nothing reads, are not computed.
+template <int R>
+__device__ __forceinline__ void store_planes(const uint4 (&t)[(R + 2) / 2], uint32_t singles, uint32_t* planes) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t h[R + 2], l[R + 2];
 #pragma unroll
-        for (int i = 0; i < R; ++i) any |= ~C.dead[i];
-        if (vh) *nvh = 0;
-        if (__ballot(any != 0) == 0) {  // the usual case: no survivor in the wave
+    for (int u = 0; u < (R + 2) / 2; ++u) {
+        h[2 * u] = t[u].x;
+        l[2 * u] = t[u].y;
+        h[2 * u + 1] = t[u].z;
+        l[2 * u + 1] = t[u].w;
+    }
 #pragma unroll
-            for (int i = 0; i < R; ++i) hit[i] = 0;
-            return;
-        }
-        if (WV && p.nchunks > kWaveVerifyChunks && __popcll(__ballot(any != 0)) <= kWaveVerifyLanes) {
-            // survivors in position order (lowest lane first, then its words
-            // and bits), each counted by the whole wave; a verified survivor
-            // is marked dead, a hit set in hit[]
-            const uint32_t lane = threadIdx.x & 63u;
+    for (int c = 0; c < 4; ++c) {
+        if (singles >> c & 1u) {
 #pragma unroll
-            for (int i = 0; i < R; ++i) hit[i] = 0;
-            for (;;) {
-                uint32_t mine = 0;
-#pragma unroll
-                for (int i = 0; i < R; ++i) mine |= ~C.dead[i];
-                const uint64_t bal = __ballot(mine != 0);
-                if (bal == 0) break;
-                const uint32_t owner = (uint32_t)__builtin_ctzll(bal);
-                int fi = 0;
-                uint32_t fb = 0;
-#pragma unroll
-                for (int i = R - 1; i >= 0; --i)
-                    if (~C.dead[i]) {
-                        fi = i;
-                        fb = __builtin_ctz(~C.dead[i]);
-                    }
-                const uint64_t mine_pos = 32 * (B + (uint64_t)fi) + fb;
-                const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)mine_pos, owner);
-                const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(mine_pos >> 32), owner);
-                const uint64_t pos = ((uint64_t)hi << 32) | lo;
-                const uint32_t c = count_window_wave(src.text4, src.image, p.nchunks, pos, p.k, lane);
-                if (lane == owner) {
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (i == fi) {
-                            C.dead[i] |= 1u << fb;
-                            if (c <= p.k) hit[i] |= 1u << fb;
-                        }
-                }
-                // hits come in position order: the first kWaveHits are kept
-                // (position << 16 | count) for the caller's output
-                if (vh && c <= p.k) {
-                    if (*nvh < kWaveHits && lane == owner) vh[*nvh] = (pos << 16) | c;
-                    ++*nvh;
-                }
+            for (int w = 0; w < R + 2; ++w) {
+                const uint32_t hx = (c & 2) ? ~h[w] : h[w];
+                const uint32_t lx = (c & 1) ? ~l[w] : l[w];
+                planes[(c * (R + 2) + w) * 64 + lane] = hx | lx;
             }
-#pragma unroll
-            for (int i = 0; i < R; ++i) nh += __builtin_popcount(hit[i]);
-            return;
         }
+    }
+}
+
+template <int R>
+__device__ __forceinline__ void lds_set(uint32_t w, const uint32_t* planes, uint32_t (&X)[4][R]) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t c = w & 3u, q = (w >> 2) & 1u;
+    const uint32_t* src = planes + (c * (R + 2) + q) * 64 + lane;
+    uint32_t P[R + 1];
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            uint32_t alive = ~C.dead[i];
-            uint32_t h = 0;
-            while (alive) {
-                const uint32_t b = __builtin_ctz(alive);
-                alive &= alive - 1u;
-                const uint32_t c = count_window(src.text4, src.image, p.nchunks, 32 * (B + i) + b, p.k);
-                if (c <= p.k) h |= 1u << b;
-            }
-            hit[i] = h;
-            nh += __builtin_popcount(h);
+    for (int i = 0; i <= R; ++i) P[i] = src[i * 64];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t r = (w >> (6 + 5 * u)) & 31u;
+#pragma unroll
+        for (int i = 0; i < R; ++i) X[u][i] = align(P[i + 1], P[i], r);
+    }
+}
+
+template <int R, int L, int NG>
+__device__ __forceinline__ void fixed_filter(const uint32_t* planes, const uint32_t (&sw)[2 * NG], uint32_t init,
+                                             uint32_t (&dead)[R]) {
+    Counters<R, L> C;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        C.dead[i] = 0;
+        if constexpr (L > 0) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) C.S[l][i] = 0u - (init >> l & 1u);
         }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        uint32_t X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
+        lds_set<R>(sw[2 * g], planes, X);
+        add2<0, R, L>(C, X[0], X[1], c0a);
+        add2<0, R, L>(C, X[2], X[3], c0b);
+        add2<1, R, L>(C, c0a, c0b, c1a);
+        lds_set<R>(sw[2 * g + 1], planes, X);
+        add2<0, R, L>(C, X[0], X[1], c0a);
+        add2<0, R, L>(C, X[2], X[3], c0b);
+        add2<1, R, L>(C, c0a, c0b, c1b);
+        add2<2, R, L>(C, c1a, c1b, c2);
+        if constexpr (L >= 3) add1<3, R, L>(C, c2);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) dead[i] = C.dead[i];
+}
+
+// Windows of lane word i (window 32*(B+i) + bit) inside [win_begin, win_end).
+template <int R>
+__device__ __forceinline__ void valid_windows(const TileSrc& src, uint64_t B, uint32_t (&valid)[R]) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const uint64_t w0 = 32 * (B + i);
+        uint32_t v = 0;
+        if (w0 < src.win_end && w0 + 32 > src.win_begin) {
+            const uint32_t lo = src.win_begin > w0 ? (uint32_t)(src.win_begin - w0) : 0u;
+            const uint32_t hi = src.win_end < w0 + 32 ? (uint32_t)(src.win_end - w0) : 32u;
+            v = (hi == 32u ? ~0u : ((1u << hi) - 1u)) & ~((1u << lo) - 1u);
+        }
+        valid[i] = v;
     }
 }
 

@@ -44,6 +44,23 @@ def test_bench_plain_contract():
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0
 
 
+def test_bench_genome_line_carries_latency_and_the_oracle_check():
+    """The default workload's line: the scan's roofline, the oracle on every
+    host core with its list compared to the GPU's, and the served form's
+    p50/p99 on the same resident text."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "genome", "--n", "20000000", "--steps", "3", "--warmup", "1", timeout=400)
+    check_contract(r)
+    assert r["roofline"]["bound"] == "hbm"
+    cb = r["cpu_baseline"]
+    assert cb["cores"] == len(os.sched_getaffinity(0)) and cb["cpu_count"] >= cb["cores"]
+    assert "equals the oracle's" in r["config"]["oracle_check"]
+    lat = r["latency_ms"]
+    assert 0 < lat["p50"] <= lat["p99"] <= lat["max"]
+    assert r["config"]["served"]["queries"] > 1000
+
+
 def test_bench_served_contract():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

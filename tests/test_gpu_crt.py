@@ -105,3 +105,49 @@ def test_crt_hits_equal_scan(pm, m, k):
     assert np.array_equal(sel, pos.cpu().numpy()) and np.array_equal(c[sel], cnt.cpu().numpy())
     wp, wc = oracle_hits(text, pat, k)
     assert np.array_equal(sel, wp) and np.array_equal(c[sel], wc)
+
+
+def test_crt_beyond_2_32_windows(pm):
+    """A 4.4e9-base text (windows past 2^31 and 2^32): the route's counts at
+    most k are the early-stop scan's hits with the same counts, found chunk
+    by chunk (no single selection over more than 2^28 windows), and its
+    counts on ranges straddling 2^31, 2^32, the transform blocks next to
+    them and the text's end equal the oracle's."""
+    from oracle import reference as ref
+
+    from paper_1611_06115_amd import synth
+
+    n = 4_400_000_000
+    rnd = random.Random(2 ** 31)
+    text = synth.iid_text(n, seed=synth.SEED0 + 91)
+    pat = rand_pattern(rnd, 100, 0.2, "ACGTRYN")
+    m, k = len(pat), 3
+    sites = [(1 << 31) - 40, (1 << 32) - 60, (1 << 32) + 50, n - m - 5]  # disjoint copies
+    for p0 in sites:
+        for j, cls in enumerate(ref.parse(pat)):
+            text[p0 + j] = ord(rnd.choice(sorted(cls)))
+    say(f"crt beyond 2^32: n={n} m={m} k={k} plants {sites}")
+    ascii_dev = torch.from_numpy(text).cuda()
+    t = pm.encode_text(ascii_dev)
+    torch.cuda.synchronize()
+    t.check()
+    del ascii_dev
+    torch.cuda.empty_cache()
+    c = pm.crt_counts(t, pat)
+    nw = n - m + 1
+    assert c.numel() == nw
+    chunk = 1 << 28
+    sel = torch.cat([torch.nonzero(c[lo:min(nw, lo + chunk)] <= k).flatten() + lo for lo in range(0, nw, chunk)])
+    pos, cnt = pm.scan(t, pm.Pattern(pat), k)
+    say(f"  {sel.numel()} windows at most {k}, scan {pos.numel()} hits")
+    assert torch.equal(sel, pos) and torch.equal(c[sel], cnt.to(torch.int32))
+    found = dict(zip(pos.cpu().tolist(), cnt.cpu().tolist()))
+    assert all(found.get(p0) == 0 for p0 in sites)
+    per = (1 << 20) - m + 1  # windows per transform block
+    ranges = [((1 << 31) - 500, (1 << 31) + 500), ((1 << 32) - 500, (1 << 32) + 500), (nw - 300, nw)]
+    for x in (1 << 31, 1 << 32):
+        b = x // per
+        ranges += [(b * per - 300, b * per + 300), ((b + 1) * per - 300, (b + 1) * per + 300)]
+    for lo, hi in ranges:
+        got = c[lo:hi].cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, oracle_counts(text, pat, lo, hi)), (lo, hi)

@@ -360,12 +360,11 @@ def test_long_m_workload(pm):
             assert planted <= set(got[0].tolist())
 
 
-def test_genome_workload_sampled(pm):
+def test_genome_workload_full(pm):
     """Full genome-scale scan (3.1e9 bases, m = 256, k = 4) in the launch
-    configuration the benchmark times: every planted copy within the budget
-    is reported with its distance, every reported count is the oracle's
-    count of that window, and on seeded window ranges (the first and last
-    windows included) the hit lists equal the oracle's."""
+    configuration the benchmark times: the whole hit list equals a full
+    oracle pass over every window (a few seconds on the host's cores), and
+    every planted copy within the budget is reported with its distance."""
     from paper_1611_06115_amd import synth
 
     w = synth.genome()
@@ -377,25 +376,15 @@ def test_genome_workload_sampled(pm):
     t.check()
     del ascii_dev
     torch.cuda.empty_cache()
-    P = pm.Pattern(pat)
-    pos, cnt = gpu_hits(pm, t, P, k)
-    sets = oracle.parse(pat)
-    m = len(sets)
+    pos, cnt = gpu_hits(pm, t, pm.Pattern(pat), k)
     found = dict(zip(pos.tolist(), cnt.tolist()))
     for _, p, d in w.plants:
         if d <= k:
             assert found.get(p) == d, (p, d)
-    for p, c in zip(pos.tolist(), cnt.tolist()):
-        assert oracle.counts(w.text[p:p + m], sets).tolist() == [c]
-    rnd = random.Random(4)
-    nw = w.n - m + 1
-    ranges = [(0, 3_000_000), (nw - 3_000_000, nw)]
-    ranges += [(s, s + 2_000_000) for s in (rnd.randrange(0, nw - 2_000_000) for _ in range(8))]
-    ranges += [(p - 1000, p + 1000) for _, p, d in w.plants[:8]]
-    for b, e in ranges:
-        want = oracle_hits(w.text, pat, k, win_begin=b, win_end=e)
-        sel = (pos >= b) & (pos < e)
-        assert_same((pos[sel], cnt[sel]), want, f"genome range {b},{e}")
+    import os
+
+    want = oracle_hits(w.text, pat, k, threads=len(os.sched_getaffinity(0)))
+    assert_same((pos, cnt), want, "genome, every window")
 
 
 def test_mscale_workload(pm):
