@@ -130,6 +130,25 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
                   int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev,
                   void* ws_dev, uint64_t ws_bytes, void* stream);
 
+/* pm_scan without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid allocation.  Same arguments and results as pm_scan
+ * minus ws_dev/ws_bytes.  Its scratch (per-tile hit counts, staged hits) is
+ * a static 32 MiB device array of the library, one per GPU it runs on, held
+ * until the process ends; the call allocates no device memory (its first
+ * call on a device looks up that device's copy of the array).  The window
+ * range [win_begin, win_end) (after clipping to [0, n-m+1)) may span at most
+ * pm_scan_noalloc_max_windows() windows, else PM_ERR_WORKSPACE (scan a longer
+ * text in several ranges).  The scratch needs no initialisation and keeps the
+ * last call's contents; every call on one GPU shares it, so calls that can
+ * overlap on the same GPU (other streams, other host threads) race and must
+ * be serialised by the caller. */
+uint64_t pm_scan_noalloc_max_windows(void);
+pm_status pm_scan_noalloc(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m,
+                          uint32_t k, const void* image_dev, uint64_t win_begin, uint64_t win_end,
+                          int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity,
+                          uint64_t* n_hits_dev, void* stream);
+
 /* Scan of a text kept in host memory (Sect. 2.6's split into pieces with an
  * m-1 overlap).  ascii_host: n bases of A/C/G/T (either case) in host
  * memory; allocated with hipHostMalloc (pinned) the copies run at the full

@@ -334,6 +334,47 @@ hipError_t mark_end(hipStream_t s) {
 // ---------------------------------------------------------------------------
 namespace {
 
+// Scratch of pm_scan_noalloc: one copy per device, held until the process
+// ends.  Host code never uses the array's name as an address (in host code
+// it is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+constexpr uint64_t kStaticScratchBytes = 32ull << 20;
+__device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+// Tiles (and windows) one pm_scan_noalloc call may cover: the largest T
+// whose workspace layout fits the scratch.
+constexpr uint64_t static_max_tiles() {
+    uint64_t t = (kStaticScratchBytes - 8ull * kMaxRanges - 512) / (4 + 8ull * kCap);
+    while (t > 0 && ((4 * t + 255) & ~255ull) + ((8ull * kMaxRanges + 255) & ~255ull) + 8ull * kCap * t >
+                        kStaticScratchBytes)
+        --t;
+    return t;
+}
+constexpr uint64_t kStaticMaxTiles = static_max_tiles();
+// a window range [b, e) needs at most (e - b + 63) / 32 + 1 blocks from the
+// even block at or below b, in tiles of 64 * kR blocks
+constexpr uint64_t kStaticMaxWindows = (kStaticMaxTiles - 1) * 64ull * kR * 32 - 64;
+static_assert(ws_layout(kStaticMaxTiles).bytes <= kStaticScratchBytes, "scratch layout");
+
+// The device address of `scratch` on the current device, looked up once
+// per device (with that device current) and kept.
+pm_status static_scratch(uint8_t** out) {
+    static std::mutex mu;
+    static std::map<int, uint8_t*> addr;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(PM_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch");
+        it = addr.emplace(dev, reinterpret_cast<uint8_t*>(ptr)).first;
+    }
+    *out = it->second;
+    return PM_OK;
+}
+
 // One scan: argument checks, the plan, the count and place kernels on
 // stream `stream`.  `ws` holds lay.bytes bytes; tile_limit > 0 bounds the
 // tiles of the window range (a layout sized for a fixed number of tiles), 0
@@ -494,6 +535,26 @@ pm_status pm_scan(const void* text_dev, uint64_t n, const uint8_t* codes, uint32
     if (ws_bytes < pm_scan_workspace_bytes(n)) return fail(PM_ERR_WORKSPACE, "workspace too small");
     return scan_launch(text_dev, n, codes, m, k, image_dev, win_begin, win_end, pos_dev, cnt_dev, capacity,
                        n_hits_dev, reinterpret_cast<uint8_t*>(ws_dev), ws_layout(max_tiles(n)), 0, stream);
+}
+
+uint64_t pm_scan_noalloc_max_windows(void) { return kStaticMaxWindows; }
+
+pm_status pm_scan_noalloc(const void* text_dev, uint64_t n, const uint8_t* codes, uint32_t m, uint32_t k,
+                          const void* image_dev, uint64_t win_begin, uint64_t win_end, int64_t* pos_dev,
+                          uint16_t* cnt_dev, uint64_t capacity, uint64_t* n_hits_dev, void* stream) {
+    // the size limit first: it needs no device
+    const uint64_t nw = m <= n ? n - m + 1 : 0;
+    const uint64_t end = std::min(win_end, nw);
+    if (win_begin < end && end - win_begin > kStaticMaxWindows)
+        return fail(PM_ERR_WORKSPACE, "window range of " + std::to_string(end - win_begin) +
+                                          " windows exceeds the static scratch's " +
+                                          std::to_string(kStaticMaxWindows) + " per call");
+    uint8_t* scratch_dev = nullptr;
+    if (const pm_status st = static_scratch(&scratch_dev); st != PM_OK) return st;
+    // the layout is sized for the largest call; the tile count of this
+    // call's window range is checked against it in scan_launch
+    return scan_launch(text_dev, n, codes, m, k, image_dev, win_begin, win_end, pos_dev, cnt_dev, capacity,
+                       n_hits_dev, scratch_dev, ws_layout(kStaticMaxTiles), kStaticMaxTiles, stream);
 }
 
 }  // extern "C"

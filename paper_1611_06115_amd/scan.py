@@ -47,6 +47,8 @@ def lib():
             "pm_pattern_image": ([vp, u32, vp, u64], i32),
             "pm_scan_workspace_bytes": ([u64], u64),
             "pm_scan": ([vp, u64, vp, u32, u32, vp, u64, u64, vp, vp, u64, vp, vp, u64, vp], i32),
+            "pm_scan_noalloc_max_windows": ([], u64),
+            "pm_scan_noalloc": ([vp, u64, vp, u32, u32, vp, u64, u64, vp, vp, u64, vp, vp], i32),
             "pm_expected_hits": ([vp, u32, u32, u64, ctypes.POINTER(ctypes.c_double)], i32),
             "pm_scan_batch_workspace_bytes": ([u64, u32, vp, vp, vp], u64),
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
@@ -227,6 +229,26 @@ def scan_async(text: Text, pattern: Pattern, k: int, ws: Workspace, win_begin: i
         ctypes.c_void_p(ws.pos.data_ptr()), ctypes.c_void_p(ws.cnt.data_ptr()), ws.capacity,
         ctypes.c_void_p(ws.n_hits.data_ptr()), ctypes.c_void_p(ws.ws.data_ptr()), ws.ws.numel(),
         _stream(stream)))
+
+
+def noalloc_max_windows() -> int:
+    """Windows one pm_scan_noalloc call may cover (its static scratch)."""
+    return int(lib().pm_scan_noalloc_max_windows())
+
+
+def scan_noalloc_async(text: Text, pattern: Pattern, k: int, pos, cnt, n_hits, win_begin: int = 0,
+                       win_end: int | None = None, stream=None) -> None:
+    """Enqueue one pm_scan_noalloc (no workspace: the library's static
+    scratch) into caller tensors pos (int64), cnt (uint16) and n_hits (one
+    int64); the capacity is pos.numel()."""
+    if win_end is None:
+        win_end = UINT64_MAX
+    img = pattern.image(text.data.device)
+    check(lib().pm_scan_noalloc(
+        ctypes.c_void_p(text.data.data_ptr()), text.n, pattern.codes.ctypes.data, pattern.m, int(k),
+        ctypes.c_void_p(img.data_ptr()), int(win_begin), int(win_end),
+        ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(cnt.data_ptr()), int(pos.numel()),
+        ctypes.c_void_p(n_hits.data_ptr()), _stream(stream)))
 
 
 def crt_counts_workspace_bytes(n: int, m: int) -> int:

@@ -205,3 +205,19 @@ def test_batch_capacities_are_bounded():
                                       b.out_off.ctypes.data, b.capacity.ctypes.data, 0, n, dummy, dummy, dummy,
                                       dummy, dummy, 1 << 62, None, None)
         assert st == -1, caps
+
+
+def test_noalloc_rejects_a_range_beyond_its_scratch_without_a_device():
+    """pm_scan_noalloc checks the window range against its static scratch
+    before it touches any device: a 3e9-window range is PM_ERR_WORKSPACE
+    (the pointers here are never dereferenced)."""
+    import ctypes
+
+    limit = scan.noalloc_max_windows()
+    assert 1 << 29 <= limit < 3_000_000_000
+    codes = scan.encode_pattern("ACGTACGT")
+    fake = ctypes.c_void_p(1 << 12)
+    st = scan.lib().pm_scan_noalloc(fake, 3_000_000_000, codes.ctypes.data, codes.size, 2, fake, 0,
+                                    scan.UINT64_MAX, fake, fake, 16, fake, None)
+    assert st == -4  # PM_ERR_WORKSPACE
+    assert "static scratch" in scan.lib().pm_last_error_detail().decode()
