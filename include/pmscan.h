@@ -149,6 +149,61 @@ pm_status pm_scan_noalloc(const void* text_dev, uint64_t n, const uint8_t* codes
                           int64_t* pos_dev, uint16_t* cnt_dev, uint64_t capacity,
                           uint64_t* n_hits_dev, void* stream);
 
+/* ------------------------------------------------------------------------ *
+ * FASTA input -- the paper scans a chromosome read from a FASTA file
+ * (Sect. 3); its text alphabet is Table 1's four bases.  Reading of a real
+ * assembly: records are separate texts; lower-case (soft-masked) letters are
+ * the same bases; any other sequence letter (N or another IUPAC code, '-',
+ * '*') is an unknown base, for which eq. (4) has no pair value, so a window
+ * covering one has no count and is never reported; a window never spans two
+ * records.  Positions are offsets in the concatenation of the records'
+ * letters (headers, line breaks and blanks removed).
+ * ------------------------------------------------------------------------ */
+
+typedef struct pm_fasta pm_fasta;
+
+/* Parse FASTA text (host memory, `len` bytes): '>' header lines (the name is
+ * the text up to the first blank), sequence lines, ';' comment lines, any
+ * line breaks.  *out receives a handle owning the parsed data (free it with
+ * pm_fasta_free).  PM_ERR_SYMBOL for a byte that is not a sequence letter, a
+ * sequence before the first header, or no header at all. */
+pm_status pm_fasta_parse(const char* data, uint64_t len, pm_fasta** out);
+void pm_fasta_free(pm_fasta* f);
+
+/* Bases of all records, concatenated, and their ASCII letters (host memory
+ * owned by the handle; A, C, G, T upper case, unknown bases written as 'A'):
+ * the caller copies them to the device and encodes them with
+ * pm_encode_text. */
+uint64_t pm_fasta_length(const pm_fasta* f);
+const uint8_t* pm_fasta_bases(const pm_fasta* f);
+
+/* Records: name (owned by the handle), offset and length in the bases. */
+uint32_t pm_fasta_record_count(const pm_fasta* f);
+pm_status pm_fasta_record(const pm_fasta* f, uint32_t i, const char** name, uint64_t* offset,
+                          uint64_t* length);
+
+/* Maximal runs of unknown bases (offset and length), ascending. */
+uint64_t pm_fasta_unknown_run_count(const pm_fasta* f);
+pm_status pm_fasta_unknown_run(const pm_fasta* f, uint64_t i, uint64_t* start, uint64_t* length);
+
+/* The window ranges [begin[r], end[r]) of a pattern of length m that lie in
+ * one record and cover no unknown base, ascending and disjoint: *count gets
+ * their number; the first `cap` are written to begin/end (host). */
+pm_status pm_fasta_window_ranges(const pm_fasta* f, uint32_t m, uint64_t* begin, uint64_t* end,
+                                 uint64_t cap, uint64_t* count);
+
+/* pm_scan over those window ranges of the encoded concatenation (text_dev,
+ * pm_fasta_length(f) bases): the hits of every range, in ascending position
+ * order, the first `capacity` to pos_dev/cnt_dev; *n_hits (host) receives the
+ * total.  ws_dev: at least pm_scan_fasta_workspace_bytes(f) bytes, 256-byte
+ * aligned.  Returns when the scan is complete (it waits on `stream` after
+ * each range to place the next one's hits). */
+uint64_t pm_scan_fasta_workspace_bytes(const pm_fasta* f);
+pm_status pm_scan_fasta(const pm_fasta* f, const void* text_dev, const uint8_t* codes, uint32_t m,
+                        uint32_t k, const void* image_dev, int64_t* pos_dev, uint16_t* cnt_dev,
+                        uint64_t capacity, uint64_t* n_hits, void* ws_dev, uint64_t ws_bytes,
+                        void* stream);
+
 /* Scan of a text kept in host memory (Sect. 2.6's split into pieces with an
  * m-1 overlap).  ascii_host: n bases of A/C/G/T (either case) in host
  * memory; allocated with hipHostMalloc (pinned) the copies run at the full

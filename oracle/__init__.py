@@ -130,5 +130,35 @@ def scan(text, sets, k: int, threads: int = 1, win_begin: int = 0, win_end: int 
     return pos[:kept], cnt[:kept], int(total)
 
 
+def fasta_scan(data: bytes, pattern: str, k: int, threads: int = 1):
+    """The FASTA reading (see reference.fasta_scan) for larger inputs: records
+    split into maximal runs of A/C/G/T, each run scanned by the brute force
+    above, positions shifted to offsets in the records' concatenation.
+    Returns (positions int64, counts uint16)."""
+    sets = parse(pattern)
+    m = len(sets)
+    text = data.decode("ascii") if isinstance(data, (bytes, bytearray)) else data
+    pos_all, cnt_all = [], []
+    offset = 0
+    for _, seq in reference.fasta_records(text):
+        i = 0
+        while i < len(seq):
+            if seq[i] not in "ACGT":
+                i += 1
+                continue
+            j = i
+            while j < len(seq) and seq[j] in "ACGT":
+                j += 1
+            if j - i >= m:
+                pos, cnt, _ = scan(seq[i:j], sets, k, threads=threads)
+                pos_all.append(pos + offset + i)
+                cnt_all.append(cnt)
+            i = j
+        offset += len(seq)
+    if not pos_all:
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.uint16)
+    return np.concatenate(pos_all), np.concatenate(cnt_all)
+
+
 def hardware_threads() -> int:
     return os.cpu_count() or 1

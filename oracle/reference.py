@@ -221,3 +221,48 @@ def reverse_complement_text(text: str) -> str:
 def reverse_complement_sets(sets: list) -> list[frozenset]:
     comp = {"A": "T", "C": "G", "G": "C", "T": "A"}
     return [frozenset(comp[b] for b in s) for s in reversed(sets)]
+
+
+# --- FASTA input -------------------------------------------------------------
+#
+# Reading (the paper is silent; Sect. 3 scans a chromosome FASTA file and
+# Table 1 codes only A, C, G, T): records are separate texts; lower case is
+# the same base; any other sequence letter is an unknown base, for which
+# eq. (4) has no pair value, so a window covering one has no count; a window
+# never spans two records.  Positions are offsets in the concatenation of
+# the records' letters (line breaks and headers removed).
+
+def fasta_records(data: str) -> list[tuple[str, str]]:
+    """(name, sequence) per '>' record; sequence letters upper-cased, line
+    breaks and blanks dropped; ';' lines are comments."""
+    records: list[tuple[str, list[str]]] = []
+    for line in data.splitlines():
+        if line.startswith(">"):
+            fields = line[1:].split()
+            records.append((fields[0] if fields else "", []))
+        elif line.startswith(";"):
+            continue
+        else:
+            letters = "".join(line.split())
+            if letters:
+                if not records:
+                    raise ValueError("sequence before the first header")
+                records[-1][1].append(letters.upper())
+    return [(name, "".join(parts)) for name, parts in records]
+
+
+def fasta_scan(data: str, sets: list, k: int) -> list[tuple[int, int]]:
+    """[(offset, c)] for every window inside one record, made only of the
+    bases A, C, G, T, with c = #{j : t[i+j] not in S_j} <= k; ascending."""
+    m = len(sets)
+    out = []
+    offset = 0
+    for _, seq in fasta_records(data):
+        for i in range(len(seq) - m + 1):
+            window = seq[i:i + m]
+            if all(ch in BASES for ch in window):
+                c = sum(1 for j in range(m) if window[j] not in sets[j])
+                if c <= k:
+                    out.append((offset + i, c))
+        offset += len(seq)
+    return out

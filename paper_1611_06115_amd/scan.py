@@ -50,6 +50,17 @@ def lib():
             "pm_scan_noalloc_max_windows": ([], u64),
             "pm_scan_noalloc": ([vp, u64, vp, u32, u32, vp, u64, u64, vp, vp, u64, vp, vp], i32),
             "pm_expected_hits": ([vp, u32, u32, u64, ctypes.POINTER(ctypes.c_double)], i32),
+            "pm_fasta_parse": ([ctypes.c_char_p, u64, ctypes.POINTER(vp)], i32),
+            "pm_fasta_free": ([vp], None),
+            "pm_fasta_length": ([vp], u64),
+            "pm_fasta_bases": ([vp], vp),
+            "pm_fasta_record_count": ([vp], u32),
+            "pm_fasta_record": ([vp, u32, ctypes.POINTER(ctypes.c_char_p), u64p, u64p], i32),
+            "pm_fasta_unknown_run_count": ([vp], u64),
+            "pm_fasta_unknown_run": ([vp, u64, u64p, u64p], i32),
+            "pm_fasta_window_ranges": ([vp, u32, vp, vp, u64, u64p], i32),
+            "pm_scan_fasta_workspace_bytes": ([vp], u64),
+            "pm_scan_fasta": ([vp, vp, vp, u32, u32, vp, vp, vp, u64, u64p, vp, u64, vp], i32),
             "pm_scan_batch_workspace_bytes": ([u64, u32, vp, vp, vp], u64),
             "pm_scan_batch": ([vp, u64, u32, vp, vp, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp, u64, vp, vp],
                               i32),
@@ -342,6 +353,100 @@ def scan(text: Text, pattern: Pattern | str, k: int, win_begin: int = 0, win_end
         (torch.cuda.current_stream() if stream is None else stream).synchronize()
         total = int(ws.n_hits.item())
     return ws.pos[:total].clone(), ws.cnt[:total].clone()
+
+
+# --- FASTA input -----------------------------------------------------------------
+
+class Fasta:
+    """A parsed FASTA file (pm_fasta_parse): records, their bases
+    concatenated (unknown bases written as 'A'), and the runs of unknown
+    bases.  The scan reports only windows inside one record that cover no
+    unknown base; positions are offsets in the concatenation."""
+
+    def __init__(self, data: bytes | str):
+        if isinstance(data, str):
+            data = data.encode("ascii")
+        h = ctypes.c_void_p()
+        check(lib().pm_fasta_parse(data, len(data), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_file(cls, path: str) -> "Fasta":
+        with open(path, "rb") as f:
+            return cls(f.read())
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.pm_fasta_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    @property
+    def n(self) -> int:
+        return int(lib().pm_fasta_length(self._h))
+
+    def bases(self) -> np.ndarray:
+        """The concatenated bases (uint8 ASCII, a copy)."""
+        n = self.n
+        if n == 0:
+            return np.zeros(0, dtype=np.uint8)
+        ptr = lib().pm_fasta_bases(self._h)
+        return np.ctypeslib.as_array((ctypes.c_uint8 * n).from_address(ptr)).copy()
+
+    def records(self) -> list:
+        """[(name, offset, length)] per record."""
+        out = []
+        for i in range(int(lib().pm_fasta_record_count(self._h))):
+            name = ctypes.c_char_p()
+            off, ln = ctypes.c_uint64(), ctypes.c_uint64()
+            check(lib().pm_fasta_record(self._h, i, ctypes.byref(name), ctypes.byref(off), ctypes.byref(ln)))
+            out.append((name.value.decode(), off.value, ln.value))
+        return out
+
+    def unknown_runs(self) -> list:
+        """[(offset, length)] of the maximal runs of unknown bases."""
+        out = []
+        for i in range(int(lib().pm_fasta_unknown_run_count(self._h))):
+            s, ln = ctypes.c_uint64(), ctypes.c_uint64()
+            check(lib().pm_fasta_unknown_run(self._h, i, ctypes.byref(s), ctypes.byref(ln)))
+            out.append((s.value, ln.value))
+        return out
+
+    def window_ranges(self, m: int) -> list:
+        count = ctypes.c_uint64()
+        check(lib().pm_fasta_window_ranges(self._h, int(m), None, None, 0, ctypes.byref(count)))
+        b = np.zeros(max(count.value, 1), dtype=np.uint64)
+        e = np.zeros(max(count.value, 1), dtype=np.uint64)
+        check(lib().pm_fasta_window_ranges(self._h, int(m), b.ctypes.data, e.ctypes.data, count.value,
+                                           ctypes.byref(count)))
+        return list(zip(b[:count.value].tolist(), e[:count.value].tolist()))
+
+    def encode(self, device=None, stream=None) -> Text:
+        """The concatenated bases encoded in device memory (pm_encode_text)."""
+        return encode_text(self.bases(), device=device, stream=stream)
+
+
+def scan_fasta(fa: Fasta, text: Text, pattern: Pattern | str, k: int, capacity: int = 1 << 16, stream=None):
+    """pm_scan_fasta: (positions int64, counts uint16) device tensors of the
+    windows inside one record, covering no unknown base, with at most k
+    mismatches; re-runs with an exact buffer when the hits exceed capacity."""
+    import torch
+
+    if isinstance(pattern, str):
+        pattern = Pattern(pattern)
+    dev = text.data.device
+    img = pattern.image(dev)
+    ws = torch.empty(int(lib().pm_scan_fasta_workspace_bytes(fa._h)), dtype=torch.uint8, device=dev)
+    total = ctypes.c_uint64()
+    while True:
+        pos = torch.empty(max(capacity, 1), dtype=torch.int64, device=dev)
+        cnt = torch.empty(max(capacity, 1), dtype=torch.uint16, device=dev)
+        check(lib().pm_scan_fasta(fa._h, ctypes.c_void_p(text.data.data_ptr()), pattern.codes.ctypes.data,
+                                  pattern.m, int(k), ctypes.c_void_p(img.data_ptr()),
+                                  ctypes.c_void_p(pos.data_ptr()), ctypes.c_void_p(cnt.data_ptr()), int(capacity),
+                                  ctypes.byref(total), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+        if total.value <= capacity:
+            return pos[:total.value], cnt[:total.value]
+        capacity = int(total.value)
 
 
 # --- batched scan ----------------------------------------------------------------

@@ -367,3 +367,44 @@ def test_pins_catch_planted_mistakes(mutant):
             hist = np.bincount(mutant(text, ref.parse(pat)), minlength=m + 1).tolist()
             caught |= hist != ref.debruijn_histogram(ref.parse(pat))
     assert caught
+
+
+def test_fasta_reading_pinned_by_hand():
+    """The FASTA reading (records separate, lower case folded, a window
+    covering a non-ACGT letter or crossing records has no count): the
+    oracle's two routes give the hits worked out by hand in
+    tests/golden/fasta_reading.txt."""
+    from oracle import reference as ref
+
+    rows = golden_lines("fasta_reading.txt")
+    fa = "\n".join(" ".join(r[1:]) for r in rows if r[0] == "fasta") + "\n"
+    for r in rows:
+        if r[0] != "query":
+            continue
+        p, k = r[1], int(r[2])
+        want = [] if r[3:] == ["none"] else [tuple(map(int, x.split(":"))) for x in r[3:]]
+        assert ref.fasta_scan(fa, ref.parse(p), k) == want, p
+        pos, cnt = oracle.fasta_scan(fa.encode(), p, k)
+        assert list(zip(pos.tolist(), cnt.tolist())) == want, p
+
+
+def test_fasta_reading_reduces_to_the_plain_scan():
+    """One record of A/C/G/T only is the plain scan of its sequence; upper
+    and lower case give the same hits; splitting a record at an unknown
+    letter gives the hits of the two parts (offsets shifted)."""
+    import random
+
+    from oracle import reference as ref
+
+    rnd = random.Random(11)
+    seq = "".join(rnd.choice("ACGT") for _ in range(400))
+    sets = ref.parse("A[CG]TN-G"[:5] + "AC")
+    for k in range(4):
+        plain = ref.scan(seq, sets, k)
+        assert ref.fasta_scan(">x\n" + seq + "\n", sets, k) == plain
+        assert ref.fasta_scan(">x\n" + seq.lower() + "\n", sets, k) == plain
+        cut = 173
+        split = ref.fasta_scan(">x\n" + seq[:cut] + "N" + seq[cut + 1:] + "\n", sets, k)
+        left = ref.scan(seq[:cut], sets, k)
+        right = [(i + cut + 1, c) for i, c in ref.scan(seq[cut + 1:], sets, k)]
+        assert split == left + right
