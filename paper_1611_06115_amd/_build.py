@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmscan.so")
-SOURCES = ["pmscan.hip", "plan.cpp", "batch.hip", "server.hip", "hostscan.hip", "ntt.hip", "fasta.cpp"]
+SOURCES = ["pmscan.hip", "plan.cpp", "batch.hip", "server.hip", "hostscan.hip", "ntt.hip", "fasta.cpp", "fasta_scan.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = [
