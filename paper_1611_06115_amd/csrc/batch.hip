@@ -41,6 +41,13 @@ namespace {
 
 constexpr int TPB = kThreads;
 constexpr int kMaxGroup = 16;
+// chunks of 32 positions a survivor's exact count loads at a time: two keep
+// the verification's registers below the filter's
+constexpr uint32_t kVerifyChunks = 2;
+// an exhaustive filter shares little per tile across patterns (only the raw
+// planes), so its groups hold 1/kExhGroupDiv of the group size: shorter
+// items, which do not hold a wave for long
+constexpr uint32_t kExhGroupDiv = 8;
 constexpr uint32_t kSkip = 0xFFu;  // variant of a pattern that cannot have hits
 
 struct BatchPattern {
@@ -49,7 +56,7 @@ struct BatchPattern {
     uint64_t stage_off;   // staging area, in hits
     uint64_t nw;          // windows: n - m + 1 (0 when m > n)
     uint32_t cap_sub;     // staged hits per sub-range
-    uint32_t variant;     // exhaustive << 3 | levels, or kSkip
+    uint32_t variant;     // fixed groups << 4 | exhaustive << 3 | levels, or kSkip
     uint32_t index;       // the caller's index of the pattern
     uint32_t pad_[1];
 };
@@ -113,11 +120,13 @@ __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) 
 }
 
 // One pattern on one tile: filter, verification, and in-order append of the
-// hits to the pattern's staging area for this sub-range.
-template <int R, int L, bool EXH>
+// hits to the pattern's staging area for this sub-range.  A singleton filter
+// reads the tile's mismatch planes from the wave's LDS region (`planes`), an
+// exhaustive one the raw planes in `s`.
+template <int R, int L, bool EXH, int NG>
 __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& bp, uint32_t sub,
                                               uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
-                                              uint32_t count_before) {
+                                              const uint32_t* planes, uint32_t count_before) {
     TileSrc src;
     src.text4 = a.text4;
     src.image = a.images + bp.image_off;
@@ -129,7 +138,26 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& b
     const bool interior = 32 * T0 >= src.win_begin && 32 * (T0 + 64ull * R) <= src.win_end;
     Counters<R, L> C;
     uint32_t hit[R], nh;
-    tile_filter<R, L, EXH, false>(src, bp.plan, B, interior, s, C, hit, nh);
+    if constexpr (EXH) {
+        tile_filter<R, L, true, false>(src, bp.plan, B, interior, s, C, hit, nh);
+    } else if constexpr (NG > 0) {
+        // NG groups of full sets and no tail: the unrolled filter
+        uint32_t sw[2 * NG], dead[R];
+#pragma unroll
+        for (int g = 0; g < 2 * NG; ++g) sw[g] = bp.plan.slot[g];
+        fixed_filter<R, L, NG, 2>(planes, sw, bp.plan.init, dead);
+        if (!interior) {
+            uint32_t valid[R];
+            valid_windows<R>(src, B, valid);
+#pragma unroll
+            for (int i = 0; i < R; ++i) dead[i] |= ~valid[i];
+        }
+        verify_survivors<R, false, kVerifyChunks>(src, bp.plan, B, dead, hit, nh);
+    } else {
+        init_counters<R, L>(src, bp.plan, B, interior, C);
+        planes_filter<R, L>(planes, bp.plan, C);
+        verify_survivors<R, false, kVerifyChunks>(src, bp.plan, B, C.dead, hit, nh);
+    }
     if (__ballot(nh != 0) == 0) return 0;
     uint32_t total;
     uint32_t idx = count_before + wave_exclusive(nh, total);
@@ -150,58 +178,88 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& b
     return total;
 }
 
-// Counter depth L of a pattern's filter decides its code path.  Two kernels:
-// WIDE = false takes L <= 4 (k - #'-' <= 15), WIDE = true takes L = 5 or 6,
-// so that the common kernel is not sized for the deepest counters.  A group's
-// patterns share the filter kind EXH, so an item runs one of two pattern
-// loops: singleton filters (which need the mismatch planes) or exhaustive
-// filters (which need the raw planes).
-template <int R, bool EXH, bool WIDE>
-__device__ __forceinline__ uint32_t run_pattern(const BatchArgs& a, CPattern& bp, uint32_t sub,
-                                                uint64_t T0, uint64_t wlo, uint64_t whi, const Lane<R>& s,
-                                                uint32_t before) {
-    switch (bp.variant & 7u) {
-#define PM_V(L) \
-    case L: return pattern_tile<R, L, EXH>(a, bp, sub, T0, wlo, whi, s, before);
-        PM_V(0) PM_V(1) PM_V(2) PM_V(3) PM_V(4)
-#undef PM_V
-        default: break;
-    }
-    if constexpr (WIDE) {
-        switch (bp.variant & 7u) {
-            case 5: return pattern_tile<R, 5, EXH>(a, bp, sub, T0, wlo, whi, s, before);
-            case 6: return pattern_tile<R, 6, EXH>(a, bp, sub, T0, wlo, whi, s, before);
-            default: break;
-        }
-    }
-    return 0;
-}
-
-template <int R, bool EXH, bool WIDE>
+// The patterns of an item share their variant: filter kind EXH, counter depth
+// L and, for an unrolled singleton filter, its NG groups (0: the loop
+// filter), so the item's whole tile loop is one code path.  A singleton item
+// writes each tile's four mismatch planes to the wave's LDS region once for
+// all its patterns.
+template <int R, bool EXH, int L, int NG>
 __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it, uint64_t blo, uint64_t wlo,
-                                         uint64_t whi, uint32_t* cnt) {
+                                         uint64_t whi, uint32_t* cnt, uint32_t* planes) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t tile = 64ull * R;
-    for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
-        // text of the tile from its first block (filter windows start at 0)
-        uint4 txt[(R + 2) / 2];
+    auto load = [&](uint64_t T0, uint4 (&t)[(R + 2) / 2]) {
         const uint32_t g0 = (uint32_t)(T0 >> 1) + lane * (R / 2);
 #pragma unroll
-        for (int u = 0; u < (R + 2) / 2; ++u) txt[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
+        for (int u = 0; u < (R + 2) / 2; ++u) t[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
+    };
+    for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
+        // (no prefetch: the item's patterns take long enough per tile that
+        // the other waves cover the load, and the registers are better spent
+        // on a fifth wave)
+        uint4 txt[(R + 2) / 2];
+        load(T0, txt);
         Lane<R> s;
-        make_lane<R>(txt, EXH ? 0u : 15u, s);
+        if constexpr (EXH) make_lane<R>(txt, 0u, s);
+        else store_planes<R>(txt, 15u, planes);
         for (uint32_t g = 0; g < it.count; ++g) {
             CPattern& bp = const_pattern(a.pats + it.first + g);
             const uint32_t before = __builtin_amdgcn_readfirstlane(cnt[g]);
-            const uint32_t added = run_pattern<R, EXH, WIDE>(a, bp, it.sub, T0, wlo, whi, s, before);
+            const uint32_t added = pattern_tile<R, L, EXH, NG>(a, bp, it.sub, T0, wlo, whi, s, planes, before);
             if ((threadIdx.x & 63u) == 0) cnt[g] = before + added;
         }
     }
 }
 
-template <int R, bool WIDE>
-__global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
+// Two kernels: KIND 0 takes the patterns with L <= 4 counter levels (k - #'-'
+// <= 15), singleton or exhaustive, KIND 1 those with L = 5 or 6, so that the
+// common kernel is not sized for the deepest counters.
+constexpr int kKinds = 2;
+
+__host__ __device__ constexpr int kind_of(uint32_t variant) { return (variant & 7u) >= 5u ? 1 : 0; }
+
+template <int R, int KIND>
+__device__ __forceinline__ void run_variant(const BatchArgs& a, const BatchItem& it, uint32_t variant, uint64_t blo,
+                                            uint64_t wlo, uint64_t whi, uint32_t* cnt, uint32_t* planes) {
+    if constexpr (KIND == 0) {
+        switch (variant & 0x7Fu) {
+#define PM_V(L)                                                                             \
+    case L: run_item<R, false, L, 0>(a, it, blo, wlo, whi, cnt, planes); return;           \
+    case 0x10 | L: run_item<R, false, L, 1>(a, it, blo, wlo, whi, cnt, planes); return;    \
+    case 0x20 | L: run_item<R, false, L, 2>(a, it, blo, wlo, whi, cnt, planes); return;    \
+    case 0x30 | L: run_item<R, false, L, 3>(a, it, blo, wlo, whi, cnt, planes); return;    \
+    case 0x40 | L: run_item<R, false, L, 4>(a, it, blo, wlo, whi, cnt, planes); return;    \
+    case 0x08 | L: run_item<R, true, L, 0>(a, it, blo, wlo, whi, cnt, planes); return;
+            PM_V(0) PM_V(1) PM_V(2) PM_V(3) PM_V(4)
+#undef PM_V
+            default: return;
+        }
+    } else {
+        switch (variant & 15u) {
+            case 5: run_item<R, false, 5, 0>(a, it, blo, wlo, whi, cnt, planes); return;
+            case 6: run_item<R, false, 6, 0>(a, it, blo, wlo, whi, cnt, planes); return;
+            case 13: run_item<R, true, 5, 0>(a, it, blo, wlo, whi, cnt, planes); return;
+            case 14: run_item<R, true, 6, 0>(a, it, blo, wlo, whi, cnt, planes); return;
+            default: return;
+        }
+    }
+}
+
+// The common kernel at R = 4 is held to 96 registers, five waves per SIMD
+// (the exhaustive filter's paths spill a few registers for it).
+template <int R, int KIND>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(KIND == 0 && R == 4 ? 5 : 1)))
+void batch_kernel(BatchArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
+    // per-pattern running hit counts of this item, in the wave's LDS slice
+    // (indexed by the pattern's place in the group, which is not a
+    // compile-time constant, so registers would be addressed indirectly)
+    __shared__ uint32_t s_cnt[TPB / 64][kMaxGroup];
+    // mismatch planes of the current tile, one region per wave (singleton
+    // filters only)
+    __shared__ uint32_t s_planes[TPB / 64][4 * (R + 2) * 64];
+    const uint32_t wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t* cnt = s_cnt[wv];
     while (true) {
         uint32_t item = 0;
         if (lane == 0) item = atomicAdd(a.queue, 1u);
@@ -213,16 +271,8 @@ __global__ __launch_bounds__(TPB) void batch_kernel(BatchArgs a) {
         const uint64_t bhi = blo + a.span_blocks;
         const uint64_t wlo = 32 * blo > a.win_begin ? 32 * blo : a.win_begin;
         const uint64_t whi = 32 * bhi < a.win_end ? 32 * bhi : a.win_end;
-        // per-pattern running hit counts of this item, in the wave's LDS slice
-        // (indexed by the pattern's place in the group, which is not a
-        // compile-time constant, so registers would be addressed indirectly)
-        __shared__ uint32_t s_cnt[TPB / 64][kMaxGroup];
-        uint32_t* cnt = s_cnt[threadIdx.x >> 6];
         if (lane < (uint32_t)kMaxGroup) cnt[lane] = 0;
-        if (wlo < whi) {
-            if (const_pattern(a.pats + it.first).variant & 8u) run_item<R, true, WIDE>(a, it, blo, wlo, whi, cnt);
-            else run_item<R, false, WIDE>(a, it, blo, wlo, whi, cnt);
-        }
+        if (wlo < whi) run_variant<R, KIND>(a, it, const_pattern(a.pats + it.first).variant, blo, wlo, whi, cnt, s_planes[wv]);
         if (lane < it.count)
             a.counts[(uint64_t)const_pattern(a.pats + it.first + lane).index * a.n_sub + it.sub] = cnt[lane];
     }
@@ -369,6 +419,17 @@ struct BatchLayout {
     uint64_t n_items_max;
 };
 
+// Groups of a singleton plan that the unrolled filter takes (1 to 4 groups of
+// full sets, no tail, at most 4 counter levels), else 0 (the loop filter).
+uint32_t fixed_groups(const ScanPlan& p) {
+    if (p.exhaustive || p.n_slots == 0 || p.levels > 4 || p.n_groups < 1 || p.n_groups > 4 ||
+        p.n_sets != 2 * p.n_groups || p.n_slots != 8 * p.n_groups)
+        return 0;
+    for (uint32_t t = 0; t < p.n_sets; ++t)
+        if ((p.slot[t] >> 3 & 7u) != 4u) return 0;
+    return p.n_groups;
+}
+
 BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, uint64_t win_begin,
                        uint64_t win_end) {
     BatchShape sh;
@@ -418,7 +479,7 @@ BatchLayout batch_layout(uint32_t count, const uint32_t* m, const uint64_t* capa
     L.items = off;
     off = align256(off + sizeof(BatchItem) * L.n_items_max);
     L.queue = off;
-    off = align256(off + 8);
+    off = align256(off + 4 * kKinds);
     L.counts = off;
     off = align256(off + 4ull * count * sh.S);
     L.staged = off;
@@ -567,7 +628,7 @@ pm_status batch_run(const BatchCall& c) {
             bp.nw = e.m <= n ? n - e.m + 1 : 0;
             bp.index = p;
             const bool skip = bp.plan.keff < 0 || bp.nw == 0 || bp.nw <= win_begin;
-            bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels;
+            bp.variant = skip ? kSkip : (bp.plan.exhaustive ? 8u : 0u) | bp.plan.levels | fixed_groups(bp.plan) << 4;
             if (with_images) build_image(e.codes, e.m, img_words + 4 * L.image_off[p]);
             // cost per tile: filter slots, plus a full count per window without a filter
             cost[p] = skip ? 0.0
@@ -613,21 +674,22 @@ pm_status batch_run(const BatchCall& c) {
     for (uint32_t i = 0; i < count;) {
         uint32_t j = i;
         double cs = 0;
-        while (j < count && j - i < sh.G && sorted[j].variant == sorted[i].variant) cs += cost[order[j++]];
+        const uint32_t gmax = (sorted[i].variant & 8u) ? std::max(1u, sh.G / kExhGroupDiv) : sh.G;
+        while (j < count && j - i < gmax && sorted[j].variant == sorted[i].variant) cs += cost[order[j++]];
         groups.push_back({i, j - i, cs});
         i = j;
     }
     std::stable_sort(groups.begin(), groups.end(), [](const Group& x, const Group& y) { return x.cost > y.cost; });
-    // common items first, then the items of patterns with 5 or 6 counter levels
-    uint64_t n_items = 0, n_common = 0;
-    auto is_wide = [&](const Group& g) { return (sorted[g.first].variant & 7u) >= 5u; };
-    for (int pass = 0; pass < 2; ++pass) {
+    // items by kernel kind (common, deep counters), each kind's items in a
+    // run of their own, costly first
+    uint64_t n_items = 0, kind_end[kKinds] = {0, 0};
+    for (int kind = 0; kind < kKinds; ++kind) {
         for (const Group& g : groups) {
-            if (g.cost == 0.0 || is_wide(g) != (pass == 1)) continue;
+            if (g.cost == 0.0 || kind_of(sorted[g.first].variant) != kind) continue;
             if (n_items + sh.S > L.n_items_max) return set_error(PM_ERR_ARG, "internal: too many work items");
             for (uint32_t sub = 0; sub < sh.S; ++sub) items[n_items++] = {g.first, g.count, sub, 0};
         }
-        if (pass == 0) n_common = n_items;
+        kind_end[kind] = n_items;
     }
 
     uint8_t* ws = reinterpret_cast<uint8_t*>(c.ws_dev);
@@ -657,21 +719,18 @@ pm_status batch_run(const BatchCall& c) {
     a.win_end = win_end;
     a.wb0 = sh.wb0;
     a.span_blocks = sh.span_blocks;
-    // two launches at most: the common kernel, and the deep-counter one on
-    // its own queue word (queue + 1) over the remaining items
+    // one launch per kind that has items, each on its own queue word
     if ((e = mark_begin(s)) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
-    if (n_common > 0) {
-        BatchFn fn = sh.R == 4 ? batch_kernel<4, false> : batch_kernel<6, false>;
-        a.n_items = (uint32_t)n_common;
-        fn<<<batch_grid(fn, n_common), TPB, 0, s>>>(a);
-        if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
-    }
-    if (n_items > n_common) {
-        BatchFn fn = sh.R == 4 ? batch_kernel<4, true> : batch_kernel<6, true>;
+    static constexpr BatchFn kFns[2][kKinds] = {{batch_kernel<4, 0>, batch_kernel<4, 1>},
+                                                {batch_kernel<6, 0>, batch_kernel<6, 1>}};
+    for (int kind = 0; kind < kKinds; ++kind) {
+        const uint64_t first = kind ? kind_end[kind - 1] : 0;
+        if (kind_end[kind] == first) continue;
+        BatchFn fn = kFns[sh.R == 4 ? 0 : 1][kind];
         BatchArgs w = a;
-        w.items = a.items + n_common;
-        w.n_items = (uint32_t)(n_items - n_common);
-        w.queue = a.queue + 1;
+        w.items = a.items + first;
+        w.n_items = (uint32_t)(kind_end[kind] - first);
+        w.queue = a.queue + kind;
         fn<<<batch_grid(fn, w.n_items), TPB, 0, s>>>(w);
         if ((e = hipGetLastError()) != hipSuccess) return set_error(PM_ERR_HIP, hipGetErrorString(e));
     }

@@ -428,6 +428,11 @@ pm_status scan_launch(const void* text_dev, uint64_t n, const uint8_t* codes, ui
     a.range_sum = reinterpret_cast<unsigned long long*>(ws + lay.range_sum);
     a.staged = reinterpret_cast<unsigned long long*>(ws + lay.staged);
     a.n_tiles = (uint32_t)n_tiles;
+    // interior tiles: the first whose first window is at or after win_begin,
+    // up to the last whose windows all lie before win_end
+    const uint64_t first_block = (win_begin + 31) >> 5, end_block = win_end >> 5;
+    a.int_lo = (uint32_t)std::min<uint64_t>(n_tiles, (first_block - wb0 + tile_blocks - 1) / tile_blocks);
+    a.int_hi = end_block >= wb0 ? (uint32_t)std::min<uint64_t>(n_tiles, (end_block - wb0) / tile_blocks) : 0u;
     const unsigned grid = persistent_grid(fn.count, n_tiles);
     a.n_ranges = grid;
 

@@ -169,15 +169,15 @@ __device__ __forceinline__ void add1(Counters<R, L>& c, uint32_t (&a)[R]) {
 
 // Exact count of one window, all m positions (pattern image), stopping once
 // the count exceeds `limit` (then the value returned is only known to exceed
-// it).  Chunks of 32 positions are taken four at a time, their loads issued
-// together, so a long pattern's count waits on a quarter of the load round
-// trips.
+// it).  Chunks of 32 positions are taken V at a time, their loads issued
+// together, so a long pattern's count waits on 1/V of the load round trips
+// (fewer at a time hold fewer registers).
+template <uint32_t V = 4>
 __device__ uint32_t count_window(const uint4* __restrict__ text4, const uint4* __restrict__ image,
                                  uint32_t nchunks, uint64_t s, uint32_t limit) {
     const uint2* text = reinterpret_cast<const uint2*>(text4);
     const uint64_t q = s >> 5;
     const uint32_t r = (uint32_t)s & 31u;
-    constexpr uint32_t V = 4;
     uint2 w0 = text[q];
     uint32_t cnt = 0;
     for (uint32_t c0 = 0; c0 < nchunks; c0 += V) {
@@ -289,8 +289,9 @@ __device__ __forceinline__ void make_lane(const uint4 (&t)[(R + 2) / 2], uint32_
 // with survivors in at most kWaveVerifyLanes lanes counts them one at a time
 // with all its lanes (position order), keeping the first kWaveHits hits as
 // (position << 16 | count) in vh (count of all such hits in *nvh); dead[] is
-// consumed.  Otherwise each lane counts its own survivors.
-template <int R, bool WV, class Plan>
+// consumed.  Otherwise each lane counts its own survivors (count_window with
+// CV chunks at a time).
+template <int R, bool WV, uint32_t CV = 4, class Plan>
 __device__ __forceinline__ void verify_survivors(const TileSrc& src, const Plan& p, uint64_t B, uint32_t (&dead)[R],
                                                  uint32_t (&hit)[R], uint32_t& nh, unsigned long long* vh = nullptr,
                                                  uint32_t* nvh = nullptr) {
@@ -357,7 +358,7 @@ __device__ __forceinline__ void verify_survivors(const TileSrc& src, const Plan&
         while (alive) {
             const uint32_t b = __builtin_ctz(alive);
             alive &= alive - 1u;
-            const uint32_t c = count_window(src.text4, src.image, p.nchunks, 32 * (B + i) + b, p.k);
+            const uint32_t c = count_window<CV>(src.text4, src.image, p.nchunks, 32 * (B + i) + b, p.k);
             if (c <= p.k) h |= 1u << b;
         }
         hit[i] = h;
@@ -365,16 +366,11 @@ __device__ __forceinline__ void verify_survivors(const TileSrc& src, const Plan&
     }
 }
 
-// Filter + verification of one tile for one pattern: hit[i] gets the windows
-// of lane word i (window 32*(B+i) + bit) with at most k mismatches; C keeps the
-// filter counters (the exact counts when the plan is exhaustive).  `s` holds
-// the lane's text planes starting at the plan's filter window.
-template <int R, int L, bool EXH, bool WV, class Plan>
-__device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
-                                            const Lane<R>& s, Counters<R, L>& C, uint32_t (&hit)[R],
-                                            uint32_t& nh, unsigned long long* vh = nullptr,
-                                            uint32_t* nvh = nullptr) {
-    // ---- valid windows of each lane word ------------------------------------
+// Counters at the plan's start value; windows outside [win_begin, win_end)
+// start dead.
+template <int R, int L, class Plan>
+__device__ __forceinline__ void init_counters(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
+                                              Counters<R, L>& C) {
     // (windows outside [win_begin, win_end) start dead; `interior` says the
     // whole tile lies inside, which holds for all tiles but the edge ones)
 #pragma unroll
@@ -395,6 +391,18 @@ __device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, u
             for (int l = 0; l < L; ++l) C.S[l][i] = (p.init >> l & 1u) ? ~0u : 0u;
         }
     }
+}
+
+// Filter + verification of one tile for one pattern: hit[i] gets the windows
+// of lane word i (window 32*(B+i) + bit) with at most k mismatches; C keeps the
+// filter counters (the exact counts when the plan is exhaustive).  `s` holds
+// the lane's text planes starting at the plan's filter window.
+template <int R, int L, bool EXH, bool WV, class Plan>
+__device__ __forceinline__ void tile_filter(const TileSrc& src, const Plan& p, uint64_t B, bool interior,
+                                            const Lane<R>& s, Counters<R, L>& C, uint32_t (&hit)[R],
+                                            uint32_t& nh, unsigned long long* vh = nullptr,
+                                            uint32_t* nvh = nullptr) {
+    init_counters<R, L>(src, p, B, interior, C);
 
     // ---- filter ---------------------------------------------------------------
     // groups of 8 slots into the counters: a full-adder tree per group (pairs
@@ -495,50 +503,112 @@ __device__ __forceinline__ void store_planes(const uint4 (&t)[(R + 2) / 2], uint
     }
 }
 
-template <int R>
-__device__ __forceinline__ void lds_set(uint32_t w, const uint32_t* planes, uint32_t (&X)[4][R]) {
+// The RW+1 plane words of a set (its base c and word offset q) from lane word
+// i0 on (RS words per base in the planes) ...
+template <int RS, int RW>
+__device__ __forceinline__ void lds_words(uint32_t w, const uint32_t* planes, int i0, uint32_t (&P)[RW + 1]) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t c = w & 3u, q = (w >> 2) & 1u;
-    const uint32_t* src = planes + (c * (R + 2) + q) * 64 + lane;
-    uint32_t P[R + 1];
+    const uint32_t* src = planes + (c * RS + q + i0) * 64 + lane;
 #pragma unroll
-    for (int i = 0; i <= R; ++i) P[i] = src[i * 64];
+    for (int i = 0; i <= RW; ++i) P[i] = src[i * 64];
+}
+
+// ... and its four slots' mismatch words for those RW lane words (shift r_u).
+template <int RW>
+__device__ __forceinline__ void align_set(uint32_t w, const uint32_t (&P)[RW + 1], uint32_t (&X)[4][RW]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const uint32_t r = (w >> (6 + 5 * u)) & 31u;
 #pragma unroll
-        for (int i = 0; i < R; ++i) X[u][i] = align(P[i + 1], P[i], r);
+        for (int i = 0; i < RW; ++i) X[u][i] = align(P[i + 1], P[i], r);
     }
 }
 
-template <int R, int L, int NG>
+// The lane words are taken RW at a time (RW divides R): fewer counters and
+// mismatch words are live at once, for one more plane word read per set and
+// part.
+template <int R, int L, int NG, int RW = R>
 __device__ __forceinline__ void fixed_filter(const uint32_t* planes, const uint32_t (&sw)[2 * NG], uint32_t init,
                                              uint32_t (&dead)[R]) {
-    Counters<R, L> C;
+    static_assert(R % RW == 0, "the parts must cover the lane words");
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-        C.dead[i] = 0;
-        if constexpr (L > 0) {
+    for (int part = 0; part < R / RW; ++part) {
+        const int i0 = part * RW;
+        Counters<RW, L> C;
 #pragma unroll
-            for (int l = 0; l < L; ++l) C.S[l][i] = 0u - (init >> l & 1u);
+        for (int i = 0; i < RW; ++i) {
+            C.dead[i] = 0;
+            if constexpr (L > 0) {
+#pragma unroll
+                for (int l = 0; l < L; ++l) C.S[l][i] = 0u - (init >> l & 1u);
+            }
         }
-    }
+        // the next set's plane words are read before this set is counted (two
+        // register sets in turn); the compiler issues all of a part's reads
+        // ahead, so that the wave waits for LDS about once per part
+        uint32_t P[2][RW + 1];
+        lds_words<R + 2, RW>(sw[0], planes, i0, P[0]);
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-        uint32_t X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
-        lds_set<R>(sw[2 * g], planes, X);
+        for (int g = 0; g < NG; ++g) {
+            uint32_t X[4][RW], c0a[RW], c0b[RW], c1a[RW], c1b[RW], c2[RW];
+            lds_words<R + 2, RW>(sw[2 * g + 1], planes, i0, P[1]);
+            __builtin_amdgcn_sched_barrier(0);
+            align_set<RW>(sw[2 * g], P[0], X);
+            add2<0, RW, L>(C, X[0], X[1], c0a);
+            add2<0, RW, L>(C, X[2], X[3], c0b);
+            add2<1, RW, L>(C, c0a, c0b, c1a);
+            if (g + 1 < NG) lds_words<R + 2, RW>(sw[2 * g + 2], planes, i0, P[0]);
+            __builtin_amdgcn_sched_barrier(0);
+            align_set<RW>(sw[2 * g + 1], P[1], X);
+            add2<0, RW, L>(C, X[0], X[1], c0a);
+            add2<0, RW, L>(C, X[2], X[3], c0b);
+            add2<1, RW, L>(C, c0a, c0b, c1b);
+            add2<2, RW, L>(C, c1a, c1b, c2);
+            if constexpr (L >= 3) add1<3, RW, L>(C, c2);
+        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i) dead[i0 + i] = C.dead[i];
+        // one part at a time: its registers are free before the next starts
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Singleton filter of any plan (run-time numbers of groups and of tail sets)
+// over the mismatch planes in LDS (`planes`, laid out as for fixed_filter,
+// every base present): the groups as in fixed_filter, then the tail sets one
+// position at a time.
+template <int R, int L, class Plan>
+__device__ __forceinline__ void planes_filter(const uint32_t* planes, const Plan& p, Counters<R, L>& C) {
+    for (uint32_t g = 0; g < p.n_groups; ++g) {
+        const uint32_t w0 = p.slot[2 * g], w1 = p.slot[2 * g + 1];
+        uint32_t P[R + 1], X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
+        lds_words<R + 2, R>(w0, planes, 0, P);
+        align_set<R>(w0, P, X);
         add2<0, R, L>(C, X[0], X[1], c0a);
         add2<0, R, L>(C, X[2], X[3], c0b);
         add2<1, R, L>(C, c0a, c0b, c1a);
-        lds_set<R>(sw[2 * g + 1], planes, X);
+        lds_words<R + 2, R>(w1, planes, 0, P);
+        align_set<R>(w1, P, X);
         add2<0, R, L>(C, X[0], X[1], c0a);
         add2<0, R, L>(C, X[2], X[3], c0b);
         add2<1, R, L>(C, c0a, c0b, c1b);
         add2<2, R, L>(C, c1a, c1b, c2);
         if constexpr (L >= 3) add1<3, R, L>(C, c2);
     }
+    for (uint32_t t = 2 * p.n_groups; t < p.n_sets; ++t) {
+        const uint32_t w = p.slot[t];
+        const uint32_t cnt = (w >> 3) & 7u;
+        uint32_t P[R + 1];
+        lds_words<R + 2, R>(w, planes, 0, P);
+        for (uint32_t u = 0; u < cnt; ++u) {
+            const uint32_t r = (w >> (6 + 5 * u)) & 31u;
+            uint32_t X[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) dead[i] = C.dead[i];
+            for (int i = 0; i < R; ++i) X[i] = align(P[i + 1], P[i], r);
+            add1<0, R, L>(C, X);
+        }
+    }
 }
 
 // Windows of lane word i (window 32*(B+i) + bit) inside [win_begin, win_end).

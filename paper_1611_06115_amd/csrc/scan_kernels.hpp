@@ -31,6 +31,8 @@ struct ScanArgs {
     unsigned long long* range_sum;   // hits per count-kernel workgroup (its range of tiles)
     unsigned long long* staged;      // kCap per tile: (window offset << 16) | count
     uint32_t n_tiles, n_ranges;
+    // tiles [int_lo, int_hi) lie wholly inside [win_begin, win_end)
+    uint32_t int_lo, int_hi;
 };
 
 // The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
@@ -93,8 +95,10 @@ __device__ __forceinline__ uint64_t tile_first_block(const ScanArgs& a, uint32_t
     return a.wb0 + (uint64_t)tile * (uint64_t)(64 * R);
 }
 
-__device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint64_t T0, int R) {
-    return 32 * T0 >= a.win_begin && 32 * (T0 + 64 * (uint64_t)R) <= a.win_end;
+// Whether every window of the tile lies in [win_begin, win_end): a test of
+// the tile index alone (uniform, two scalar compares).
+__device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint32_t tile) {
+    return tile >= a.int_lo && tile < a.int_hi;
 }
 
 // Exclusive prefix of `x` over the lanes of a wave; `total` gets the sum.
@@ -241,22 +245,26 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
         Lane<R> s;
         make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
         uint32_t nvh = 0;
-        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh, s_vh[wv], &nvh);
+        tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, tile), s, C, hit, nh, s_vh[wv], &nvh);
         sum += stage_tile<R, L, EXH>(a, p, tile, T0, B, C, hit, nh, nvh, s_vh[wv]);
     }
     store_range_sum(a, sum);
 }
 
 // The same pass for a plan of NG groups of two full singleton sets (the
-// planner's usual shape), with the unrolled fixed_filter.  Each wave keeps
-// the text of its next two tiles in flight in two register buffers that it
-// uses in turn (the loop is unrolled by two so that no buffer is copied):
-// with only the next tile in flight the loads' latency is not covered and
-// the scan runs at about 3.3 TB/s whatever its instruction count.  A tile's
-// text goes to the LDS planes first; its buffer is then reloaded with the
-// tile two steps ahead while the filter runs.
+// planner's usual shape), with the unrolled fixed_filter.  A tile's text goes
+// to the LDS planes first; its register buffer is then reloaded with the
+// wave's next tile while the filter runs.  One buffer and a filter that
+// counts PM_FIXED_RW lane words at a time keep the kernel at 80 registers,
+// so that six waves share a SIMD: the other waves' filters cover the load
+// latency (with five waves and two buffers in flight the scan is about 7%
+// slower).
 #ifndef PM_FIXED_WAVES
-#define PM_FIXED_WAVES 5
+#define PM_FIXED_WAVES 6
+#endif
+// lane words the filter counts at a time
+#ifndef PM_FIXED_RW
+#define PM_FIXED_RW 2
 #endif
 // s_waitcnt with only the vector-memory count at zero (gfx9 encoding:
 // expcnt and lgkmcnt at their maxima).
@@ -273,7 +281,7 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
     // unconditional (a tile past the end reads the text's last group, never
     // used), so that the number of loads in flight is the same on every path
     // and the wait for one buffer's text does not also wait for the other's
-    load_tile_text<R>(a, p, tile_first_block(a, tile + 2 * kStep, R), buf);
+    load_tile_text<R>(a, p, tile_first_block(a, tile + kStep, R), buf);
     // keep those loads here, ahead of the filter
     __builtin_amdgcn_sched_barrier(0);
     // the slot words, read again for every tile: kept as loop invariants
@@ -286,8 +294,8 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
         sw[g] = w;
     }
     uint32_t dead[R];
-    fixed_filter<R, L, NG>(planes, sw, p.init, dead);
-    if (!tile_interior(a, T0, R)) {
+    fixed_filter<R, L, NG, PM_FIXED_RW>(planes, sw, p.init, dead);
+    if (!tile_interior(a, tile)) {
         uint32_t valid[R];
         valid_windows<R>(a.src, B, valid);
 #pragma unroll
@@ -318,13 +326,12 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
     __shared__ unsigned long long s_vh[TPB / 64][kWaveHits];
     // mismatch planes of the fixed filter, one region per wave
     __shared__ uint32_t s_planes[TPB / 64][4 * (R + 2) * 64];
-    uint4 bufA[(R + 2) / 2], bufB[(R + 2) / 2];
-    load_tile_text<R>(a, p, tile_first_block(a, tile, R), bufA);
-    load_tile_text<R>(a, p, tile_first_block(a, tile + kStep, R), bufB);
+    uint4 buf[(R + 2) / 2];
+    load_tile_text<R>(a, p, tile_first_block(a, tile, R), buf);
     // per-tile hit counts are gathered in a register across 64 tiles (lane j
     // holds the j-th) and stored together: a store in every iteration would
-    // leave loads and stores in flight together, and then every wait for a
-    // buffer's text would also wait for the other buffer
+    // leave loads and stores in flight together, and then the wait for the
+    // text would also wait for the store
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t pend = 0, k = 0, batch = tile;
     auto keep = [&](uint32_t total) {
@@ -336,16 +343,10 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
             k = 0;
         }
     };
-    while (tile < t_end) {
-        uint32_t total = fixed_tile<R, L, NG>(a, p, tile, bufA, s_planes[wv], s_vh[wv]);
+    for (; tile < t_end; tile += kStep) {
+        const uint32_t total = fixed_tile<R, L, NG>(a, p, tile, buf, s_planes[wv], s_vh[wv]);
         sum += total;
         keep(total);
-        tile += kStep;
-        if (tile >= t_end) break;
-        total = fixed_tile<R, L, NG>(a, p, tile, bufB, s_planes[wv], s_vh[wv]);
-        sum += total;
-        keep(total);
-        tile += kStep;
     }
     if (lane < k) a.counts[batch + kStep * lane] = pend;
     store_range_sum(a, sum);
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(TPB) void scan_place_kernel(ScanArgs a, ScanPlan p)
             uint32_t hit[R], nh;
             Lane<R> s;
             make_lane<R>(txt, EXH || p.n_slots == 0 ? 0u : p.singles, s);
-            tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, T0, R), s, C, hit, nh);
+            tile_filter<R, L, EXH, true>(a.src, p, B, tile_interior(a, tile), s, C, hit, nh);
             uint32_t total;
             const uint32_t excl = wave_exclusive(nh, total);
             if (nh) write_hits<R, L, EXH>(a, p, C, hit, B, pl + excl);
