@@ -101,6 +101,21 @@ __device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint32_t tile) 
     return tile >= a.int_lo && tile < a.int_hi;
 }
 
+// The waves of a SIMD are issued oldest first, so with equal shares of tiles
+// the oldest waves finish far ahead of the youngest (on the genome workload
+// the first tenth of the waves ended at 45% of the launch) and the SIMDs then
+// run short of waves for the rest of it.  A wave with more of its share left
+// runs at a higher priority (more than 1/2, 1/5 or 1/16 left: 3, 2, 1, else
+// 0): the waves of a SIMD stay close together to the end (about 13% less
+// time on that workload).
+__device__ __forceinline__ void share_priority(uint32_t left, uint32_t share) {
+    const uint64_t l = left;
+    if (2 * l > share) __builtin_amdgcn_s_setprio(3);
+    else if (5 * l > share) __builtin_amdgcn_s_setprio(2);
+    else if (16 * l > share) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 // Exclusive prefix of `x` over the lanes of a wave; `total` gets the sum.
 __device__ __forceinline__ uint32_t wave_exclusive(uint32_t x, uint32_t& total) {
     const uint32_t lane = threadIdx.x & 63u;
@@ -230,7 +245,10 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
     // the text of the wave's next tile is loaded while this one is computed
     uint4 nxt[(R + 2) / 2];
     if (tile < t_end) load_tile_text<R>(a, p, tile_first_block(a, tile, R), nxt);
-    for (; tile < t_end; tile += kStep) {
+    const uint32_t share = tile < t_end ? (t_end - tile + kStep - 1) / kStep : 0u;
+    __builtin_amdgcn_s_setprio(3);
+    for (uint32_t done = 0; tile < t_end; tile += kStep) {
+        share_priority(share - done++, share);
         const uint64_t T0 = tile_first_block(a, tile, R);
         const uint64_t B = T0 + (uint64_t)lane * R;
         uint4 txt[(R + 2) / 2];
@@ -343,7 +361,10 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
             k = 0;
         }
     };
-    for (; tile < t_end; tile += kStep) {
+    const uint32_t share = tile < t_end ? (t_end - tile + kStep - 1) / kStep : 0u;
+    __builtin_amdgcn_s_setprio(3);
+    for (uint32_t done = 0; tile < t_end; tile += kStep) {
+        share_priority(share - done++, share);
         const uint32_t total = fixed_tile<R, L, NG>(a, p, tile, buf, s_planes[wv], s_vh[wv]);
         sum += total;
         keep(total);
