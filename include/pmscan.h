@@ -231,8 +231,10 @@ pm_status pm_scan_host(const uint8_t* ascii_host, uint64_t n, const uint8_t* cod
  * bits, Sect. 1.3.5) and computed with number-theoretic transforms over text
  * blocks that overlap by m-1.  A second exact route beside pm_scan: it gives
  * every window's count whatever k, at a cost that does not depend on k.
- * text_dev: the encoded text (16-byte aligned); codes: m Table 2 codes (host;
- * m in 1..2^22, larger is PM_ERR_UNSUPPORTED).  counts_dev receives
+ * text_dev: the encoded text (16-byte aligned), n bases of any length the
+ * encoding holds (block offsets and window indexes are 64-bit; tested past
+ * 2^32 windows); codes: m Table 2 codes (host; m in 1..2^22, larger is
+ * PM_ERR_UNSUPPORTED).  counts_dev receives
  * counts_dev[i] = number of mismatches of window i, for i in [0, n-m+1)
  * (nothing when m > n).  ws_dev: 256-byte aligned, at least
  * pm_crt_counts_workspace_bytes(n, m) bytes (0 for an invalid m).  Returns
