@@ -177,10 +177,11 @@ ScanPair pick_scan_l(uint32_t L) {
     }
 }
 // Count kernels with the fixed filter: singleton plans of NG = 1..4 groups of
-// full sets and 1..4 counter levels (k - #'-' up to 15).
+// full sets and 0..4 counter levels (k - #'-' up to 15).
 template <int R, int NG>
 ScanFn pick_fixed_l(uint32_t L) {
     switch (L) {
+        case 0: return scan_fixed_kernel<R, 0, NG>;
         case 1: return scan_fixed_kernel<R, 1, NG>;
         case 2: return scan_fixed_kernel<R, 2, NG>;
         case 3: return scan_fixed_kernel<R, 3, NG>;
