@@ -205,12 +205,23 @@ ScanFn pick_fixed(const ScanPlan& p) {
         default: return nullptr;
     }
 }
+// fixed_ok: the fixed kernel's 32-bit load offsets cover the launch.
 template <int R>
-ScanPair pick_scan(const ScanPlan& p) {
+ScanPair pick_scan(const ScanPlan& p, bool fixed_ok) {
     ScanPair f = p.exhaustive ? pick_scan_l<R, true>(p.levels) : pick_scan_l<R, false>(p.levels);
-    if (f.count)
+    if (f.count && fixed_ok)
         if (ScanFn fixed = pick_fixed<R>(p)) f.count = fixed;
     return f;
+}
+
+// The fixed kernel addresses the text with 32-bit byte offsets from the
+// buffer start: tile t's lanes read bytes [tile_byte0 + t * 64 R * 8, + 64 R
+// * 8 + 16 * ((R + 2) / 2 + R / 2 * 63)), for t up to n_tiles - 1 + the
+// prefetch distance (four tiles); the buffer's size must fit too.
+bool fixed_offsets_fit(uint64_t buffer_bytes, uint64_t tile_byte0, uint64_t n_tiles) {
+    const uint64_t tile_bytes = 64ull * kR * 8;
+    const uint64_t last = tile_byte0 + (n_tiles + 4) * tile_bytes + 16ull * ((kR + 2) / 2 + kR / 2 * 63);
+    return buffer_bytes <= 0xFFFFFFFFull && last <= 0xFFFFFFFFull;
 }
 
 // Workgroups for a persistent kernel: as many as fit on the device at once
@@ -408,7 +419,8 @@ pm_status scan_launch(const void* text_dev, uint64_t n, const uint8_t* codes, ui
     if (n_tiles > (tile_limit ? tile_limit : max_tiles(n)) || n_tiles > 0xFFFFFFFFull)
         return fail(PM_ERR_ARG, "window range too large");
 
-    const ScanPair fn = pick_scan<kR>(plan);
+    const uint64_t buffer_bytes = 16 * (text_blocks(n) / 2), tile_byte0 = 8 * (wb0 + plan.fword);
+    const ScanPair fn = pick_scan<kR>(plan, fixed_offsets_fit(buffer_bytes, tile_byte0, n_tiles));
     if (!fn.count) return fail(PM_ERR_UNSUPPORTED, "counter levels out of range");
 
     ScanArgs a;
@@ -434,6 +446,9 @@ pm_status scan_launch(const void* text_dev, uint64_t n, const uint8_t* codes, ui
     const uint64_t first_block = (win_begin + 31) >> 5, end_block = win_end >> 5;
     a.int_lo = (uint32_t)std::min<uint64_t>(n_tiles, (first_block - wb0 + tile_blocks - 1) / tile_blocks);
     a.int_hi = end_block >= wb0 ? (uint32_t)std::min<uint64_t>(n_tiles, (end_block - wb0) / tile_blocks) : 0u;
+    // the fixed kernel's buffer loads (taken only when fixed_offsets_fit)
+    a.text_bytes = (uint32_t)std::min<uint64_t>(buffer_bytes, 0xFFFFFFFFull);
+    a.tile_byte0 = (uint32_t)std::min<uint64_t>(tile_byte0, 0xFFFFFFFFull);
     const unsigned grid = persistent_grid(fn.count, n_tiles);
     a.n_ranges = grid;
 

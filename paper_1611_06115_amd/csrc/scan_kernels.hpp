@@ -33,6 +33,9 @@ struct ScanArgs {
     uint32_t n_tiles, n_ranges;
     // tiles [int_lo, int_hi) lie wholly inside [win_begin, win_end)
     uint32_t int_lo, int_hi;
+    // the fixed kernel's loads: bytes of the text buffer, and the byte offset
+    // of tile 0's first group (with the plan's filter window)
+    uint32_t text_bytes, tile_byte0;
 };
 
 // The text a lane's filter needs: blocks B+fw .. B+fw+R+1 as 16-byte groups
@@ -101,6 +104,30 @@ __device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint32_t tile) 
     return tile >= a.int_lo && tile < a.int_hi;
 }
 
+// The text of tile `tile` (uniform) through a buffer resource over the whole
+// encoded text: each lane's byte offset is the tile's offset (scalar) plus
+// its own, one vector add per tile; the resource's range check clamps in
+// hardware (a load past the buffer returns zeros, like the zero padding
+// after the text), so the last tiles need no clamping arithmetic.  Only for
+// a buffer that 32-bit offsets cover (text_bytes; the launch takes the
+// generic kernel otherwise).  The same (R+2)/2 loads on every path.
+template <int R>
+__device__ __forceinline__ void load_tile(const ScanArgs& a, const __amdgpu_buffer_rsrc_t& text, uint32_t tile,
+                                          uint4 (&t)[(R + 2) / 2]) {
+    const uint32_t at = a.tile_byte0 + tile * (uint32_t)(64 * R * 8);  // 64 R blocks of 8 bytes
+    const uint32_t off = (threadIdx.x & 63u) * (uint32_t)(16 * (R / 2)) + at;
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (int u = 0; u < (R + 2) / 2; ++u) {
+        const v4u v = __builtin_amdgcn_raw_buffer_load_b128(text, off + 16u * u, 0, 0);
+        t[u] = make_uint4(v.x, v.y, v.z, v.w);
+    }
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t text_resource(const ScanArgs& a) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4*>(a.text4), (short)0, (int)a.text_bytes, 0x00020000);
+}
+
 // The waves of a SIMD are issued oldest first, so with equal shares of tiles
 // the oldest waves finish far ahead of the youngest (on the genome workload
 // the first tenth of the waves ended at 45% of the launch) and the SIMDs then
@@ -108,11 +135,12 @@ __device__ __forceinline__ bool tile_interior(const ScanArgs& a, uint32_t tile) 
 // runs at a higher priority (more than 1/2, 1/5 or 1/16 left: 3, 2, 1, else
 // 0): the waves of a SIMD stay close together to the end (about 13% less
 // time on that workload).
+// (left > share / d is left * d > share for integers, in 32-bit scalar
+// compares: the 64-bit form would be vector compares.)
 __device__ __forceinline__ void share_priority(uint32_t left, uint32_t share) {
-    const uint64_t l = left;
-    if (2 * l > share) __builtin_amdgcn_s_setprio(3);
-    else if (5 * l > share) __builtin_amdgcn_s_setprio(2);
-    else if (16 * l > share) __builtin_amdgcn_s_setprio(1);
+    if (left > share / 2) __builtin_amdgcn_s_setprio(3);
+    else if (left > share / 5) __builtin_amdgcn_s_setprio(2);
+    else if (left > share / 16) __builtin_amdgcn_s_setprio(1);
     else __builtin_amdgcn_s_setprio(0);
 }
 
@@ -289,17 +317,16 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
 #define PM_WAIT_VMEM() __builtin_amdgcn_s_waitcnt(0x0F70)
 
 template <int R, int L, int NG>
-__device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan& p, uint32_t tile,
-                                               uint4 (&buf)[(R + 2) / 2], uint32_t* planes, unsigned long long* vh) {
+__device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan& p, const __amdgpu_buffer_rsrc_t& text,
+                                               uint32_t tile, uint4 (&buf)[(R + 2) / 2], uint32_t* planes,
+                                               unsigned long long* vh) {
     constexpr uint32_t kStep = TPB / 64;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t T0 = tile_first_block(a, tile, R);
-    const uint64_t B = T0 + (uint64_t)lane * R;
     store_planes<R>(buf, p.singles, planes);
     // unconditional (a tile past the end reads the text's last group, never
     // used), so that the number of loads in flight is the same on every path
-    // and the wait for one buffer's text does not also wait for the other's
-    load_tile_text<R>(a, p, tile_first_block(a, tile + kStep, R), buf);
+    load_tile<R>(a, text, tile + kStep, buf);
     // keep those loads here, ahead of the filter
     __builtin_amdgcn_sched_barrier(0);
     // the slot words, read again for every tile: kept as loop invariants
@@ -315,7 +342,7 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
     fixed_filter<R, L, NG, PM_FIXED_RW>(planes, sw, p.init, dead);
     if (!tile_interior(a, tile)) {
         uint32_t valid[R];
-        valid_windows<R>(a.src, B, valid);
+        valid_windows<R>(a.src, T0 + (uint64_t)lane * R, valid);
 #pragma unroll
         for (int i = 0; i < R; ++i) dead[i] |= ~valid[i];
     }
@@ -323,6 +350,7 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
 #pragma unroll
     for (int i = 0; i < R; ++i) any |= ~dead[i];
     if (__ballot(any != 0) == 0) return 0;  // the usual case: no survivor in the tile
+    const uint64_t B = T0 + (uint64_t)lane * R;
     uint32_t hit[R], nh, nvh = 0;
     verify_survivors<R, true>(a.src, p, B, dead, hit, nh, vh, &nvh);
     Counters<R, L> C;  // not read: the fixed filter is never exhaustive
@@ -344,8 +372,9 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
     __shared__ unsigned long long s_vh[TPB / 64][kWaveHits];
     // mismatch planes of the fixed filter, one region per wave
     __shared__ uint32_t s_planes[TPB / 64][4 * (R + 2) * 64];
+    const __amdgpu_buffer_rsrc_t text = text_resource(a);
     uint4 buf[(R + 2) / 2];
-    load_tile_text<R>(a, p, tile_first_block(a, tile, R), buf);
+    load_tile<R>(a, text, tile, buf);
     // per-tile hit counts are gathered in a register across 64 tiles (lane j
     // holds the j-th) and stored together: a store in every iteration would
     // leave loads and stores in flight together, and then the wait for the
@@ -365,7 +394,7 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
     __builtin_amdgcn_s_setprio(3);
     for (uint32_t done = 0; tile < t_end; tile += kStep) {
         share_priority(share - done++, share);
-        const uint32_t total = fixed_tile<R, L, NG>(a, p, tile, buf, s_planes[wv], s_vh[wv]);
+        const uint32_t total = fixed_tile<R, L, NG>(a, p, text, tile, buf, s_planes[wv], s_vh[wv]);
         sum += total;
         keep(total);
     }
