@@ -143,9 +143,13 @@ __device__ __forceinline__ uint32_t pattern_tile(const BatchArgs& a, CPattern& b
     } else if constexpr (NG > 0) {
         // NG groups of full sets and no tail: the unrolled filter
         uint32_t sw[2 * NG], dead[R];
+        const uint32_t* rows[2 * NG];
 #pragma unroll
-        for (int g = 0; g < 2 * NG; ++g) sw[g] = bp.plan.slot[g];
-        fixed_filter<R, L, NG, 2>(planes, sw, bp.plan.init, dead);
+        for (int g = 0; g < 2 * NG; ++g) {
+            sw[g] = bp.plan.slot[g];
+            rows[g] = set_row<R + 2>(planes, sw[g]);
+        }
+        fixed_filter<R, L, NG, 2>(rows, sw, bp.plan.init, dead);
         if (!interior) {
             uint32_t valid[R];
             valid_windows<R>(src, B, valid);

@@ -503,15 +503,19 @@ __device__ __forceinline__ void store_planes(const uint4 (&t)[(R + 2) / 2], uint
     }
 }
 
-// The RW+1 plane words of a set (its base c and word offset q) from lane word
-// i0 on (RS words per base in the planes) ...
-template <int RS, int RW>
-__device__ __forceinline__ void lds_words(uint32_t w, const uint32_t* planes, int i0, uint32_t (&P)[RW + 1]) {
+// The lane's row of a set's plane words in the LDS planes: base c and word
+// offset q of the set word w (RS words per base).
+template <int RS>
+__device__ __forceinline__ const uint32_t* set_row(const uint32_t* planes, uint32_t w) {
     const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t c = w & 3u, q = (w >> 2) & 1u;
-    const uint32_t* src = planes + (c * RS + q + i0) * 64 + lane;
+    return planes + ((w & 3u) * RS + ((w >> 2) & 1u)) * 64 + lane;
+}
+
+// The RW+1 plane words of a set from lane word i0 on ...
+template <int RW>
+__device__ __forceinline__ void lds_words(const uint32_t* row, int i0, uint32_t (&P)[RW + 1]) {
 #pragma unroll
-    for (int i = 0; i <= RW; ++i) P[i] = src[i * 64];
+    for (int i = 0; i <= RW; ++i) P[i] = row[(i0 + i) * 64];
 }
 
 // ... and its four slots' mismatch words for those RW lane words (shift r_u).
@@ -529,8 +533,8 @@ __device__ __forceinline__ void align_set(uint32_t w, const uint32_t (&P)[RW + 1
 // mismatch words are live at once, for one more plane word read per set and
 // part.
 template <int R, int L, int NG, int RW = R>
-__device__ __forceinline__ void fixed_filter(const uint32_t* planes, const uint32_t (&sw)[2 * NG], uint32_t init,
-                                             uint32_t (&dead)[R]) {
+__device__ __forceinline__ void fixed_filter(const uint32_t* const (&rows)[2 * NG], const uint32_t (&sw)[2 * NG],
+                                             uint32_t init, uint32_t (&dead)[R]) {
     static_assert(R % RW == 0, "the parts must cover the lane words");
 #pragma unroll
     for (int part = 0; part < R / RW; ++part) {
@@ -548,17 +552,17 @@ __device__ __forceinline__ void fixed_filter(const uint32_t* planes, const uint3
         // register sets in turn); the compiler issues all of a part's reads
         // ahead, so that the wave waits for LDS about once per part
         uint32_t P[2][RW + 1];
-        lds_words<R + 2, RW>(sw[0], planes, i0, P[0]);
+        lds_words<RW>(rows[0], i0, P[0]);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             uint32_t X[4][RW], c0a[RW], c0b[RW], c1a[RW], c1b[RW], c2[RW];
-            lds_words<R + 2, RW>(sw[2 * g + 1], planes, i0, P[1]);
+            lds_words<RW>(rows[2 * g + 1], i0, P[1]);
             __builtin_amdgcn_sched_barrier(0);
             align_set<RW>(sw[2 * g], P[0], X);
             add2<0, RW, L>(C, X[0], X[1], c0a);
             add2<0, RW, L>(C, X[2], X[3], c0b);
             add2<1, RW, L>(C, c0a, c0b, c1a);
-            if (g + 1 < NG) lds_words<R + 2, RW>(sw[2 * g + 2], planes, i0, P[0]);
+            if (g + 1 < NG) lds_words<RW>(rows[2 * g + 2], i0, P[0]);
             __builtin_amdgcn_sched_barrier(0);
             align_set<RW>(sw[2 * g + 1], P[1], X);
             add2<0, RW, L>(C, X[0], X[1], c0a);
@@ -583,12 +587,12 @@ __device__ __forceinline__ void planes_filter(const uint32_t* planes, const Plan
     for (uint32_t g = 0; g < p.n_groups; ++g) {
         const uint32_t w0 = p.slot[2 * g], w1 = p.slot[2 * g + 1];
         uint32_t P[R + 1], X[4][R], c0a[R], c0b[R], c1a[R], c1b[R], c2[R];
-        lds_words<R + 2, R>(w0, planes, 0, P);
+        lds_words<R>(set_row<R + 2>(planes, w0), 0, P);
         align_set<R>(w0, P, X);
         add2<0, R, L>(C, X[0], X[1], c0a);
         add2<0, R, L>(C, X[2], X[3], c0b);
         add2<1, R, L>(C, c0a, c0b, c1a);
-        lds_words<R + 2, R>(w1, planes, 0, P);
+        lds_words<R>(set_row<R + 2>(planes, w1), 0, P);
         align_set<R>(w1, P, X);
         add2<0, R, L>(C, X[0], X[1], c0a);
         add2<0, R, L>(C, X[2], X[3], c0b);
@@ -600,7 +604,7 @@ __device__ __forceinline__ void planes_filter(const uint32_t* planes, const Plan
         const uint32_t w = p.slot[t];
         const uint32_t cnt = (w >> 3) & 7u;
         uint32_t P[R + 1];
-        lds_words<R + 2, R>(w, planes, 0, P);
+        lds_words<R>(set_row<R + 2>(planes, w), 0, P);
         for (uint32_t u = 0; u < cnt; ++u) {
             const uint32_t r = (w >> (6 + 5 * u)) & 31u;
             uint32_t X[R];

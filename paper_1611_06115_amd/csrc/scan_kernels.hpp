@@ -319,7 +319,7 @@ void scan_count_kernel(ScanArgs a, ScanPlan p) {
 template <int R, int L, int NG>
 __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan& p, const __amdgpu_buffer_rsrc_t& text,
                                                uint32_t tile, uint4 (&buf)[(R + 2) / 2], uint32_t* planes,
-                                               unsigned long long* vh) {
+                                               const uint32_t* const (&rows0)[2 * NG], unsigned long long* vh) {
     constexpr uint32_t kStep = TPB / 64;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t T0 = tile_first_block(a, tile, R);
@@ -338,11 +338,22 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
         asm volatile("" : "+s"(w));
         sw[g] = w;
     }
+    // the lane's row of each set's plane words: the loop invariants rows0 for
+    // up to two groups (four vector registers), formed again for every tile
+    // for more (their registers would cost the sixth wave)
+    const uint32_t* rows[2 * NG];
+#pragma unroll
+    for (int g = 0; g < 2 * NG; ++g) rows[g] = NG <= 2 ? rows0[g] : set_row<R + 2>(planes, sw[g]);
     uint32_t dead[R];
-    fixed_filter<R, L, NG, PM_FIXED_RW>(planes, sw, p.init, dead);
+    fixed_filter<R, L, NG, PM_FIXED_RW>(rows, sw, p.init, dead);
+    // (the lane's first lane word B is formed only on the two rare paths,
+    // from an opaque copy of the lane index each, so that the compiler does
+    // not hoist it into every tile)
     if (!tile_interior(a, tile)) {
+        uint32_t l = lane;
+        asm volatile("" : "+v"(l));
         uint32_t valid[R];
-        valid_windows<R>(a.src, T0 + (uint64_t)lane * R, valid);
+        valid_windows<R>(a.src, T0 + (uint64_t)l * R, valid);
 #pragma unroll
         for (int i = 0; i < R; ++i) dead[i] |= ~valid[i];
     }
@@ -350,7 +361,9 @@ __device__ __forceinline__ uint32_t fixed_tile(const ScanArgs& a, const ScanPlan
 #pragma unroll
     for (int i = 0; i < R; ++i) any |= ~dead[i];
     if (__ballot(any != 0) == 0) return 0;  // the usual case: no survivor in the tile
-    const uint64_t B = T0 + (uint64_t)lane * R;
+    uint32_t l = lane;
+    asm volatile("" : "+v"(l));
+    const uint64_t B = T0 + (uint64_t)l * R;
     uint32_t hit[R], nh, nvh = 0;
     verify_survivors<R, true>(a.src, p, B, dead, hit, nh, vh, &nvh);
     Counters<R, L> C;  // not read: the fixed filter is never exhaustive
@@ -373,6 +386,9 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
     // mismatch planes of the fixed filter, one region per wave
     __shared__ uint32_t s_planes[TPB / 64][4 * (R + 2) * 64];
     const __amdgpu_buffer_rsrc_t text = text_resource(a);
+    const uint32_t* rows0[2 * NG];  // used for NG <= 2 (fixed_tile)
+#pragma unroll
+    for (int g = 0; g < 2 * NG; ++g) rows0[g] = NG <= 2 ? set_row<R + 2>(s_planes[wv], p.slot[g]) : nullptr;
     uint4 buf[(R + 2) / 2];
     load_tile<R>(a, text, tile, buf);
     // per-tile hit counts are gathered in a register across 64 tiles (lane j
@@ -394,7 +410,7 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
     __builtin_amdgcn_s_setprio(3);
     for (uint32_t done = 0; tile < t_end; tile += kStep) {
         share_priority(share - done++, share);
-        const uint32_t total = fixed_tile<R, L, NG>(a, p, text, tile, buf, s_planes[wv], s_vh[wv]);
+        const uint32_t total = fixed_tile<R, L, NG>(a, p, text, tile, buf, s_planes[wv], rows0, s_vh[wv]);
         sum += total;
         keep(total);
     }
