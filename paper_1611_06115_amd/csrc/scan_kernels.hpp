@@ -422,17 +422,21 @@ void scan_fixed_kernel(ScanArgs a, ScanPlan p) {
 template <typename T>
 __device__ __forceinline__ unsigned long long wave_sum(const T* x, uint64_t first, uint64_t last) {
     const uint32_t lane = threadIdx.x & 63u;
-    // four loads per lane in flight at a time
-    unsigned long long v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-    uint64_t i = first + lane;
-    for (; i + 192 < last; i += 256) {
-        v0 += x[i];
-        v1 += x[i + 64];
-        v2 += x[i + 128];
-        v3 += x[i + 192];
+    // 16 loads per lane in flight per round (1024 values): a busy segment's
+    // prefix over the range totals (up to a few thousand) takes one or two
+    // load round trips, which set the place kernel's time
+    constexpr int kV = 16;
+    unsigned long long v = 0;
+    for (uint64_t i0 = first; i0 < last; i0 += 64 * kV) {
+        T t[kV];
+#pragma unroll
+        for (int j = 0; j < kV; ++j) {
+            const uint64_t i = i0 + (uint64_t)j * 64 + lane;
+            t[j] = i < last ? x[i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kV; ++j) v += t[j];
     }
-    for (; i < last; i += 64) v0 += x[i];
-    unsigned long long v = (v0 + v1) + (v2 + v3);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
     return v;
