@@ -200,7 +200,7 @@ __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it
     for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
         // (no prefetch: the item's patterns take long enough per tile that
         // the other waves cover the load, and the registers are better spent
-        // on a fifth wave)
+        // on more waves per SIMD)
         uint4 txt[(R + 2) / 2];
         load(T0, txt);
         Lane<R> s;
