@@ -4,6 +4,7 @@ the batched scan (random launch shape) and the query server (random chunk
 count) all equal the oracle, bit for bit, on random texts, pattern lengths
 from 1 to 6000, class densities up to 50% (all symbols, '-' included) and k
 from 0 to 70."""
+import os
 import random
 import sys
 
@@ -37,7 +38,8 @@ def as_np(r):
     return r[0].cpu().numpy(), r[1].cpu().numpy()
 
 
-@pytest.mark.parametrize("case", range(40))
+# PM_SWEEP_CASES widens the sweep (a longer run of 400 cases passed as well)
+@pytest.mark.parametrize("case", range(int(os.environ.get("PM_SWEEP_CASES", "40"))))
 def test_random_sweep(pm, case):
     scan, server = pm
     rnd = random.Random(1_000_003 * (case + 1))
