@@ -453,3 +453,53 @@ def test_text_beyond_2_32_bases(pm):
         sel = (plain[0] >= b) & (plain[0] < e)
         assert_same((plain[0][sel], plain[1][sel]), oracle_hits(text, pat, k, win_begin=b, win_end=e),
                     f"range around {p0}")
+
+
+def test_text_past_32_bit_offsets(pm):
+    """A 17.6e9-base text, whose encoding (4.4 GB) is larger than 32-bit byte
+    offsets reach: the fixed count kernel, which addresses the text that way,
+    is not taken, and the genome-shaped pattern (whose plan it would take on
+    a smaller text) runs through the generic kernel.  Copies planted past
+    2^32 and 2^34 windows and at the end are found with count 0, the plain
+    and the batched lists agree, and both equal the oracle on ranges around
+    the copies."""
+    from paper_1611_06115_amd import synth
+    from oracle import reference as ref
+
+    n = 17_600_000_000
+    assert pm.lib().pm_text_bytes(n) > (1 << 32)
+    dev = torch.device("cuda")
+    say(f"text of {n} bases generated on the device")
+    ascii_dev = torch.empty(n, dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.SEED0 + 91)
+    lut = torch.tensor(list(b"ACGT"), dtype=torch.uint8, device=dev)
+    chunk = 1 << 28
+    for b in range(0, n, chunk):
+        e = min(n, b + chunk)
+        x = torch.randint(0, 4, (e - b,), dtype=torch.int64, device=dev, generator=gen)
+        ascii_dev[b:e] = lut[x]
+        del x
+    pat = synth.genome_pattern()
+    m, k = len(pat), 4
+    rnd = random.Random(2 ** 34)
+    sites = [(1 << 32) + 7, (1 << 34) + 1000, n - m - 3]
+    for p0 in sites:
+        copy = bytes(ord(rnd.choice(sorted(cls))) for cls in ref.parse(pat))
+        ascii_dev[p0:p0 + m] = torch.frombuffer(bytearray(copy), dtype=torch.uint8).to(dev)
+    t = pm.encode_text(ascii_dev)
+    torch.cuda.synchronize()
+    t.check()
+    plain = gpu_hits(pm, t, pm.Pattern(pat), k)
+    batch = pm.scan_batch(t, [pat, "ACGTACGTACGTACGTACGTACGTACGTACGT"], [k, 1])[0]
+    batch = (batch[0].cpu().numpy(), batch[1].cpu().numpy())
+    assert_same(batch, plain, "batched vs plain")
+    found = dict(zip(plain[0].tolist(), plain[1].tolist()))
+    nw = n - m + 1
+    for p0 in sites:
+        assert found.get(p0) == 0, p0
+        b, e = max(0, p0 - 500_000), min(nw, p0 + 500_000)
+        host = ascii_dev[b:e + m - 1].cpu().numpy()
+        wp, wc = oracle_hits(host, pat, k)
+        sel = (plain[0] >= b) & (plain[0] < e)
+        assert_same((plain[0][sel], plain[1][sel]), (wp + b, wc), f"range around {p0}")
