@@ -626,7 +626,7 @@ pm_status batch_run(const BatchCall& c) {
             const BatchEntry& e = c.entries[p];
             BatchPattern& bp = pats[p];
             std::memset(&bp, 0, sizeof(bp));
-            bp.plan = e.plan ? *e.plan : build_plan(e.codes, e.m, e.k, 4e-5, /*window_at_zero=*/true);
+            bp.plan = e.plan ? *e.plan : build_plan(e.codes, e.m, e.k, kBatchSurvival, /*window_at_zero=*/true);
             bp.image_off = with_images ? L.image_off[p] : e.image_off;
             bp.stage_off = L.stage_off[p];
             bp.cap_sub = L.cap_sub[p];

@@ -336,7 +336,7 @@ struct pm_server {
 
     void size_query(Query* q) {
         if (q->sized) return;
-        q->plan = build_plan(q->codes.data(), q->m, q->k, 4e-5, /*window_at_zero=*/true);
+        q->plan = build_plan(q->codes.data(), q->m, q->k, kBatchSurvival, /*window_at_zero=*/true);
         const double e = expected_hits(q->codes.data(), q->m, q->k, n);
         const double total = 2.0 * e + 64.0 * C;
         q->cap = (uint64_t)std::ceil(std::min(total, 1e18) / C);
