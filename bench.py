@@ -111,6 +111,35 @@ def valu_profile(workload: str):
     return t
 
 
+def settle(fn, stream, seconds: float, block: int = 20) -> dict:
+    """Back-to-back steps for `seconds` of GPU time, before the warm-up.
+    From an idle GPU the first ~200 genome scans run at a transient low
+    shader clock (the power management overshoots, then settles: their mean
+    is ~14% above the sustained step, single steps up to 35%), and the rate
+    then holds for seconds; timing from idle would measure that transient.
+    Returns the steps run and the mean ms per step of the first block (the
+    from-idle figure)."""
+    import torch
+
+    if seconds <= 0:
+        return {"seconds": 0, "steps": 0}
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    first, steps, spent = None, 0, 0.0
+    while spent < seconds * 1e3:
+        e0.record(stream)
+        for _ in range(block):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        if first is None:
+            first = ms / block
+        spent += ms
+        steps += block
+    return {"seconds": seconds, "steps": steps, "first_block_ms_per_step": round(first, 5)}
+
+
 def time_steps(fn, steps: int, warmup: int, stream, kernel: bool = False, samples: list | None = None):
     """Mean ms per step over `steps` timed steps (HIP events on `stream`).
     With kernel=True also the mean duration of the scan's main kernel, from
@@ -282,8 +311,11 @@ def run_plain(args):
     step = lambda: scan.scan_async(text, pat, k, ws)  # noqa: E731
     kern_each = []
     if args.flush:
+        settled = {"seconds": 0, "steps": 0}
         ms, kern_ms = time_steps_cold(step, args.steps, args.warmup, stream, samples=kern_each)
     else:
+        settled = settle(step, stream, args.settle)
+        log(f"[bench] settled: {settled}")
         ms, kern_ms = time_steps(step, args.steps, args.warmup, stream, kernel=True, samples=kern_each)
     hits = int(ws.n_hits.item())
     log(f"[bench] {args.steps} steps, {ms:.4f} ms/step (count kernel {kern_ms:.4f} ms), {hits} hits")
@@ -321,6 +353,10 @@ def run_plain(args):
         "config": {"workload": desc, "n": text.n, "m": m, "k": k, "windows": nw, "hits": hits,
                    "cache": ("cold: 512 MB written before each timed step" if args.flush
                              else "warm: steps back to back"),
+                   # steps run back to back before the warm-up, so that the
+                   # timed steps see the sustained clock (the first block's
+                   # rate is the from-idle transient)
+                   "settle": settled,
                    "count_kernel_ms": {"mean": round(kern_ms, 5), "sd": round(float(np.std(kern_each)), 5),
                                        "runs": len(kern_each)},
                    "windows_per_s": round(nw / sec, 1), "encode_kernel_ms": round(enc_ms, 4),
@@ -1007,6 +1043,8 @@ def main():
                     help="genome/small/long_m: write 512 MB before each timed step (cold Infinity Cache)")
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--settle", type=float, default=0.25,
+                    help="genome/small/long_m: seconds of back-to-back steps before the warm-up (0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-served", action="store_true", help="genome: skip the served-latency leg")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -56,6 +56,8 @@ def test_bench_genome_line_carries_latency_and_the_oracle_check():
     cb = r["cpu_baseline"]
     assert cb["cores"] == len(os.sched_getaffinity(0)) and cb["cpu_count"] >= cb["cores"]
     assert "equals the oracle's" in r["config"]["oracle_check"]
+    st = r["config"]["settle"]
+    assert st["steps"] > 0 and st["first_block_ms_per_step"] > 0
     lat = r["latency_ms"]
     assert 0 < lat["p50"] <= lat["p99"] <= lat["max"]
     assert r["config"]["served"]["queries"] > 1000
