@@ -197,20 +197,40 @@ __device__ __forceinline__ void run_item(const BatchArgs& a, const BatchItem& it
 #pragma unroll
         for (int u = 0; u < (R + 2) / 2; ++u) t[u] = a.text4[min(g0 + (uint32_t)u, a.n4_last)];
     };
-    for (uint64_t T0 = blo + ((wlo / 32 - blo) / tile) * tile; 32 * T0 < whi; T0 += tile) {
-        // (no prefetch: the item's patterns take long enough per tile that
-        // the other waves cover the load, and the registers are better spent
-        // on more waves per SIMD)
-        uint4 txt[(R + 2) / 2];
-        load(T0, txt);
-        Lane<R> s;
-        if constexpr (EXH) make_lane<R>(txt, 0u, s);
-        else store_planes<R>(txt, 15u, planes);
-        for (uint32_t g = 0; g < it.count; ++g) {
-            CPattern& bp = const_pattern(a.pats + it.first + g);
-            const uint32_t before = __builtin_amdgcn_readfirstlane(cnt[g]);
-            const uint32_t added = pattern_tile<R, L, EXH, NG>(a, bp, it.sub, T0, wlo, whi, s, planes, before);
-            if ((threadIdx.x & 63u) == 0) cnt[g] = before + added;
+    const uint64_t first = blo + ((wlo / 32 - blo) / tile) * tile;
+    if constexpr (EXH) {
+        // (no prefetch: the raw planes stay in registers through the
+        // patterns, and the exhaustive items are few and long)
+        for (uint64_t T0 = first; 32 * T0 < whi; T0 += tile) {
+            uint4 txt[(R + 2) / 2];
+            load(T0, txt);
+            Lane<R> s;
+            make_lane<R>(txt, 0u, s);
+            for (uint32_t g = 0; g < it.count; ++g) {
+                CPattern& bp = const_pattern(a.pats + it.first + g);
+                const uint32_t before = __builtin_amdgcn_readfirstlane(cnt[g]);
+                const uint32_t added = pattern_tile<R, L, EXH, NG>(a, bp, it.sub, T0, wlo, whi, s, planes, before);
+                if ((threadIdx.x & 63u) == 0) cnt[g] = before + added;
+            }
+        }
+    } else {
+        // The tile's text goes to the LDS planes, and the register buffer is
+        // then reloaded with the item's next tile while the patterns are
+        // counted: an item of one or two patterns has too little work per
+        // tile for the other waves to cover the load (the last load, past
+        // the item, reads a clamped address and is not used).
+        uint4 buf[(R + 2) / 2];
+        if (32 * first < whi) load(first, buf);
+        Lane<R> none;  // (read by the exhaustive filter only)
+        for (uint64_t T0 = first; 32 * T0 < whi; T0 += tile) {
+            store_planes<R>(buf, 15u, planes);
+            load(T0 + tile, buf);
+            for (uint32_t g = 0; g < it.count; ++g) {
+                CPattern& bp = const_pattern(a.pats + it.first + g);
+                const uint32_t before = __builtin_amdgcn_readfirstlane(cnt[g]);
+                const uint32_t added = pattern_tile<R, L, EXH, NG>(a, bp, it.sub, T0, wlo, whi, none, planes, before);
+                if ((threadIdx.x & 63u) == 0) cnt[g] = before + added;
+            }
         }
     }
 }
