@@ -479,6 +479,69 @@ def valu_calibration(target_ms: float = 3.0):
     print(json.dumps(out), flush=True)
 
 
+def run_sustained(args):
+    """The genome scan run back to back from an idle GPU for --duration
+    seconds, its step time taken in blocks of 20 steps: the power transient
+    of the first scans and the rate that holds after it (what the settle
+    phase of the default line waits out)."""
+    import numpy as np
+    import torch
+
+    from paper_1611_06115_amd import scan, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.genome(n=args.n or 3_100_000_000)
+    pattern, k = w.patterns[0], w.ks[0]
+    text = scan.encode_text(torch.from_numpy(w.text).to(dev))
+    stream = torch.cuda.current_stream()
+    stream.synchronize()
+    text.check()
+    pat = scan.Pattern(pattern)
+    ws = scan.Workspace(dev, text.n, capacity=1 << 20)
+    block = 20
+    # enough blocks for the duration at the sustained rate (~0.15 ms a step)
+    n_blocks = max(10, int(args.duration / (block * 0.15e-3)))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n_blocks + 1)]
+    for e in ev:  # creates the events
+        e.record(stream)
+    stream.synchronize()
+    time.sleep(2.0)  # an idle GPU first
+    ev[0].record(stream)
+    for b in range(n_blocks):
+        for _ in range(block):
+            scan.scan_async(text, pat, k, ws)
+        ev[b + 1].record(stream)
+        if b % 50 == 49:
+            ev[b + 1].synchronize()
+            log(f"[bench] {(b + 1) * block} steps")
+    stream.synchronize()
+    per = np.array([ev[b].elapsed_time(ev[b + 1]) / block for b in range(n_blocks)])
+    first = per[:10]  # steps 1-200
+    rest = per[10:]
+    nw = text.n - pat.m + 1
+    steady = float(rest.mean())
+    hits = int(ws.n_hits.item())
+    return {
+        "metric": "G base-pattern comparisons/sec", "value": round(nw * pat.m / (steady / 1e3) / 1e9, 2),
+        "unit": "G comparisons/s", "n_gpus": 1, "steps": int(n_blocks * block), "warmup": 0,
+        "ms_per_step": round(steady, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 bitwise (exact integer counts)", "data": "synthetic",
+        "config": {"workload": f"sustained: the genome scan (n={text.n}, m={pat.m}, k={k}) back to back from "
+                               f"an idle GPU, {n_blocks * block} steps timed in blocks of {block}",
+                   "hits": hits,
+                   "steps_1_200_ms_per_step": {"mean": round(float(first.mean()), 5),
+                                               "max_block": round(float(first.max()), 5)},
+                   "after_200_ms_per_step": {"mean": round(steady, 5), "min_block": round(float(rest.min()), 5),
+                                             "max_block": round(float(rest.max()), 5),
+                                             "sd_block": round(float(rest.std()), 5)},
+                   "blocks_of_200_steps_ms": [round(float(per[i:i + 10].mean()), 4)
+                                              for i in range(0, n_blocks, 10)]},
+        "roofline": {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+                     "traffic": None},
+    }
+
+
 def run_mscale(args):
     """The shape of the paper's m-scaling experiment (Sect. 3, Tables 5-7)
     on a synthetic text of chromosome 2's length: exact copies of m = 500,
@@ -1026,7 +1089,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale", "outofcore", "crt"])
+    ap.add_argument("--workload", default="genome", choices=["genome", "small", "long_m", "batched", "served", "mscale", "outofcore", "crt",
+                             "sustained"])
     ap.add_argument("--count", type=int, default=None, help="batched: number of patterns")
     ap.add_argument("--group", type=int, default=None, help="batched, served: patterns per text tile")
     ap.add_argument("--sub", type=int, default=None, help="batched: text sub-ranges")
@@ -1034,7 +1098,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="batched: tune the launch shape now")
     ap.add_argument("--n", type=int, default=None, help="override the text length")
     ap.add_argument("--qps", type=float, default=1000.0, help="served: arrival rate")
-    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=10.0,
+                    help="served: seconds of arrivals; sustained: seconds of back-to-back scans")
     ap.add_argument("--chunks", type=int, default=None, help="served: text chunks per revolution")
     ap.add_argument("--slots", type=int, default=None, help="served: queries scanned together")
     ap.add_argument("--arena-gib", type=float, default=64.0, help="served: device memory of the server")
@@ -1062,7 +1127,7 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the scan shards "
               "by text range with an m-1 overlap and no exchange, see the design notes", flush=True)
         raise SystemExit(2)
-    run = {"batched": run_batched, "served": run_served, "mscale": run_mscale,
+    run = {"batched": run_batched, "served": run_served, "mscale": run_mscale, "sustained": run_sustained,
            "outofcore": run_outofcore, "crt": run_crt}.get(args.workload, run_plain)
     res = run(args)
     print(json.dumps(res), flush=True)

@@ -123,3 +123,15 @@ def test_time_next_scan_brackets_the_count_kernel():
 
     with pytest.raises(scan.PMError):  # both events or neither
         scan.check(scan.lib().pm_time_next_scan(None, ctypes.c_void_p(b.cuda_event)))
+
+
+def test_bench_sustained_run():
+    """The from-idle run behind the settle phase: per-block step times, the
+    first 200 steps apart from the rest."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    r = run_bench("--workload", "sustained", "--n", "20000000", "--duration", "0.05")
+    check_contract(r)
+    c = r["config"]
+    assert c["steps_1_200_ms_per_step"]["mean"] > 0 and c["after_200_ms_per_step"]["mean"] > 0
+    assert len(c["blocks_of_200_steps_ms"]) >= 1 and r["steps"] >= 200
