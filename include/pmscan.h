@@ -266,7 +266,8 @@ typedef struct {
     uint32_t group_size;  /* patterns sharing each text tile (1..16); 0 = 8          */
     uint32_t sub_ranges;  /* text sub-ranges per pattern group (1..4096); 0 = auto:  */
                           /* about 32768 work items per call                          */
-    uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = 4                 */
+    uint32_t lane_words;  /* 32-window words per lane: 4 or 6; 0 = auto: 6 for calls */
+                          /* of 2 to 16 patterns, 4 otherwise (other values: 4)      */
     uint32_t reserved;
 } pm_batch_config;
 

@@ -459,7 +459,16 @@ BatchShape batch_shape(uint64_t n, uint32_t count, const pm_batch_config* cfg, u
                        uint64_t win_end) {
     BatchShape sh;
     sh.G = cfg && cfg->group_size ? std::min<uint32_t>(cfg->group_size, kMaxGroup) : 8;
-    sh.R = cfg && cfg->lane_words == 6 ? 6 : 4;
+    // lane words: as asked, or (0) 6 for calls of 2 to 16 patterns and 4
+    // otherwise.  Such calls make few long items, each a chain of tiles that
+    // one wave runs in order, and six lane words per tile take a third fewer
+    // links (served-pool patterns over the genome text: 10-28% less time at
+    // 2 to 8 patterns, 4% at 16, none from 32 on; a lone pattern took twice
+    // as long in one case, where the six-word kernel's three waves per SIMD
+    // hold fewer items at once than its 4096).
+    sh.R = cfg && cfg->lane_words == 6 ? 6
+           : cfg && cfg->lane_words != 0 ? 4
+           : (count >= 2 && count <= 16 ? 6 : 4);
     uint32_t S = cfg && cfg->sub_ranges ? cfg->sub_ranges : batch_auto_sub_ranges(count, cfg);
     S = std::min<uint32_t>(S, kMaxSubRanges);
     sh.S = S;
