@@ -187,6 +187,7 @@ struct Query {
 
 struct Step {
     uint32_t chunk = 0, slot = 0;
+    bool plain = false;  // one query, run by the plain scan (no status words)
     std::vector<Query*> qs;
 };
 
@@ -395,6 +396,28 @@ struct pm_server {
     bool launch_step() {
         const uint32_t slot = (uint32_t)(step_no & 1), chunk = next_chunk;
         const uint32_t count = (uint32_t)active.size();
+        // A step of one query runs the plain scan into the query's segment:
+        // one pattern makes too few work items to fill the chip in the
+        // batched kernel (a step over the genome text: ~425 us batched, ~150
+        // us plain).  Overflow is then n_hits > cap, read on the host.
+        const bool plain = count == 1 && ws_bytes >= pm_scan_workspace_bytes(n);
+        if (plain) {
+            Query* q = active[0];
+            const uint64_t out = q->region + (uint64_t)chunk * q->cap;
+            const pm_status s = pm_scan(text, n, q->codes.data(), q->m, q->k, images + q->image, (uint64_t)chunk * W,
+                                        std::min<uint64_t>(n, (uint64_t)(chunk + 1) * W), pos + out, cnt + out,
+                                        q->cap, dev_nh[slot], ws, ws_bytes, main);
+            if (s != PM_OK) {
+                fail_engine(s, pm_last_error_detail());
+                return false;
+            }
+            if (!host_nh[slot].grow(8) ||
+                !hip_ok(hipMemcpyAsync(host_nh[slot].p, dev_nh[slot], 8, hipMemcpyDeviceToHost, main),
+                        "hipMemcpyAsync") ||
+                !hip_ok(hipEventRecord(step_ev[slot], main), "hipEventRecord"))
+                return false;
+            return end_step(slot, chunk, true);
+        }
         std::vector<BatchEntry> ent(count);
         std::vector<uint32_t> ms(count);
         std::vector<uint64_t> caps(count);
@@ -448,6 +471,12 @@ struct pm_server {
                     "hipMemcpyAsync") ||
             !hip_ok(hipEventRecord(step_ev[slot], main), "hipEventRecord"))
             return false;
+        return end_step(slot, chunk, false);
+    }
+
+    // The bookkeeping of a launched step.
+    bool end_step(uint32_t slot, uint32_t chunk, bool plain) {
+        const uint32_t count = (uint32_t)active.size();
         {
             std::lock_guard<std::mutex> lk(mu);
             st.peak_active = std::max(st.peak_active, count);
@@ -455,6 +484,7 @@ struct pm_server {
         Step stp;
         stp.chunk = chunk;
         stp.slot = slot;
+        stp.plain = plain;
         stp.qs = active;
         for (Query* q : active)
             if (q->enqueued++ == 0) {
@@ -492,7 +522,7 @@ struct pm_server {
         for (size_t i = 0; i < stp.qs.size(); ++i) {
             Query* q = stp.qs[i];
             q->hits[stp.chunk] = nh[i];
-            if (sf[i]) {
+            if (stp.plain ? nh[i] > q->cap : sf[i] != 0) {
                 if (q->rescan.empty()) rescan_q.push_back(q);
                 q->rescan.push_back(stp.chunk);
             }
