@@ -146,6 +146,41 @@ def test_served_overflow_rescans(pm, chunks):
         assert_same(res[i], want, f"overflow query {i}")
 
 
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_served_overflow_one_query_steps(pm, chunks):
+    """The same overflowing queries submitted one at a time, each waited
+    for before the next: every step holds one query and runs the plain
+    scan, whose overflowed chunks are re-scanned as a batched step's are."""
+    scan, server = pm
+    rnd = random.Random(12)
+    from paper_1611_06115_amd import synth
+
+    text = synth.iid_text(2_000_000, seed=synth.SEED0 + 51)
+    pats = [rand_pattern(rnd, 40, 0.1) for _ in range(3)] + ["ACGTTGCAAC"]
+    ks = [0, 2, 1, 0]
+    for p, k in zip(pats[:3], ks):
+        plant_copies(rnd, text, p, 3000, 0)
+    for j in range(2000):
+        p0 = 900_000 + 20 * j
+        text[p0:p0 + 10] = np.frombuffer(b"ACGTTGCAAC", dtype=np.uint8)
+    t = scan.encode_text(text)
+    cfg = server.ServerConfig(chunks=chunks)
+    with server.Server(t, 128 << 20, cfg) as srv:
+        ids, res = [], []
+        for p, k in zip(pats, ks):
+            q = srv.submit(p, k)
+            srv.wait(q, 60_000)
+            ids.append(q)
+            res += collect(srv, [q])
+        st = srv.stats()
+    say(f"  stats {st}")
+    assert st["reruns"] > 0 and st["peak_active"] == 1
+    for i, (p, k) in enumerate(zip(pats, ks)):
+        want = oracle_hits(text, p, k)
+        assert want[0].size >= 1000
+        assert_same(res[i], want, f"one-query overflow {i}")
+
+
 def test_served_timestamps_and_errors(pm):
     scan, server = pm
     from paper_1611_06115_amd import synth
