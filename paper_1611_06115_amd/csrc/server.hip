@@ -187,7 +187,7 @@ struct Query {
 
 struct Step {
     uint32_t chunk = 0, slot = 0;
-    bool plain = false;  // one query, run by the plain scan (no status words)
+    bool plain = false;  // one or two queries, run by the plain scan (no status words)
     std::vector<Query*> qs;
 };
 
@@ -396,23 +396,28 @@ struct pm_server {
     bool launch_step() {
         const uint32_t slot = (uint32_t)(step_no & 1), chunk = next_chunk;
         const uint32_t count = (uint32_t)active.size();
-        // A step of one query runs the plain scan into the query's segment:
-        // one pattern makes too few work items to fill the chip in the
-        // batched kernel (a step over the genome text: ~425 us batched, ~150
-        // us plain).  Overflow is then n_hits > cap, read on the host.
-        const bool plain = count == 1 && ws_bytes >= pm_scan_workspace_bytes(n);
+        // A step of one or two queries runs the plain scan of each into its
+        // segment, one after the other on the step's stream (which keeps the
+        // workspace theirs in turn): so few patterns make too few work items
+        // to fill the chip in the batched kernel (a step over the genome
+        // text: one query ~425 us batched, ~150 us plain; two ~410 us
+        // batched, 280-380 us plain).  Overflow is then n_hits > cap, read
+        // on the host.
+        const bool plain = count <= 2 && ws_bytes >= pm_scan_workspace_bytes(n);
         if (plain) {
-            Query* q = active[0];
-            const uint64_t out = q->region + (uint64_t)chunk * q->cap;
-            const pm_status s = pm_scan(text, n, q->codes.data(), q->m, q->k, images + q->image, (uint64_t)chunk * W,
-                                        std::min<uint64_t>(n, (uint64_t)(chunk + 1) * W), pos + out, cnt + out,
-                                        q->cap, dev_nh[slot], ws, ws_bytes, main);
-            if (s != PM_OK) {
-                fail_engine(s, pm_last_error_detail());
-                return false;
+            for (uint32_t i = 0; i < count; ++i) {
+                Query* q = active[i];
+                const uint64_t out = q->region + (uint64_t)chunk * q->cap;
+                const pm_status s = pm_scan(text, n, q->codes.data(), q->m, q->k, images + q->image,
+                                            (uint64_t)chunk * W, std::min<uint64_t>(n, (uint64_t)(chunk + 1) * W),
+                                            pos + out, cnt + out, q->cap, dev_nh[slot] + i, ws, ws_bytes, main);
+                if (s != PM_OK) {
+                    fail_engine(s, pm_last_error_detail());
+                    return false;
+                }
             }
-            if (!host_nh[slot].grow(8) ||
-                !hip_ok(hipMemcpyAsync(host_nh[slot].p, dev_nh[slot], 8, hipMemcpyDeviceToHost, main),
+            if (!host_nh[slot].grow(8ull * count) ||
+                !hip_ok(hipMemcpyAsync(host_nh[slot].p, dev_nh[slot], 8ull * count, hipMemcpyDeviceToHost, main),
                         "hipMemcpyAsync") ||
                 !hip_ok(hipEventRecord(step_ev[slot], main), "hipEventRecord"))
                 return false;
